@@ -1,0 +1,162 @@
+/*
+ * pdm.h -- C ABI of libpdm: partitioned distance maps on MI355X (gfx950).
+ *
+ * Method: "Accelerating Transfer Function Update for Distance Map based Volume
+ * Rendering" (arXiv 2407.21552).  A volume of integer intensities is cut into
+ * 4x4x4 bricks (Sec. 3.1).  The intensity range [0, L) is cut into n
+ * partitions given by integer borders (Sec. 3.1).  For every partition p a
+ * partitioned occupancy map (POM) marks the bricks holding intensities of p,
+ * and its partitioned distance map (PDM) stores, per brick, the chessboard
+ * distance in bricks to the nearest occupied brick, as uint8 clamped at 255
+ * (Sec. 3.1, Sec. 3.2).  On a transfer-function (TF) change the active set S
+ * (partitions holding an intensity of non-zero opacity) is found and the new
+ * distance map is D' = min over p in S of PDM_p (Sec. 3.1, Eq. 1).  The plain
+ * method recomputes occupancy and distance map from the volume on every TF
+ * change (Sec. 2, Sec. 4.2).
+ *
+ * Occupancy reading: a brick is occupied for an intensity interval when its
+ * intensity range [min, max] meets the interval (RANGE).  POMs and the plain
+ * method use the same reading, so D' <= D holds element-wise, with equality
+ * whenever no active partition mixes zero and non-zero opacity (Sec. 3.1).
+ *
+ * Layouts (all C order, x fastest):
+ *   volume  [nz][ny][nx] of uint8 or uint16 (dtype), voxel < levels.
+ *   bricks  [Bz][By][Bx] with Bx = ceil(nx/4) etc.; G = Bx*By*Bz.
+ *   bmin/bmax [Bz][By][Bx] of the volume's dtype.
+ *   pdms    [n][Bz][By][Bx] uint8 (n*G bytes, Sec. 5 memory n*V/b^3).
+ *   dist    [Bz][By][Bx] uint8 (D' or D).
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device pointers; h_* are host pointers.  The
+ *     caller owns and allocates every buffer; the library allocates nothing
+ *     and keeps no pointer after returning.  Host arrays are read during the
+ *     call only and may be freed as soon as it returns.
+ *   - Device work is enqueued on `stream` (0 = the null stream) and the call
+ *     returns without synchronising.  There is no global state: calls are
+ *     reentrant; calls that write the same buffers must be ordered by the
+ *     caller (same stream or events).
+ *   - Arguments are validated on the host before any device work; a failed
+ *     check returns PDM_E_INVAL or PDM_E_UNSUPPORTED and enqueues nothing.
+ *     PDM_E_DEVICE reports a failed kernel launch.
+ *   - On PDM_OK every output element is written, including the empty active
+ *     set (D' = 255 everywhere).
+ */
+#ifndef PDM_H
+#define PDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDM_MAX_PARTITIONS 256  /* Table 1 goes up to 256 partitions */
+#define PDM_DIST_CAP 255        /* uint8 distances, clamped (Sec. 3.2) */
+#define PDM_BRICK 4             /* block size b = 4 (Sec. 3.1) */
+#define PDM_MAX_GRID_AXIS 65535 /* bricks per axis */
+#define PDM_MAX_GRID_X 16384    /* bricks along x */
+#define PDM_MAX_PLAIN_LEVELS 16384 /* levels accepted by the plain method */
+
+typedef enum {
+    PDM_OK = 0,
+    PDM_E_INVAL = -1,       /* bad pointer, size, dtype, levels or bounds */
+    PDM_E_RANGE = -2,       /* reserved: data-dependent range errors go to d_range_err */
+    PDM_E_UNSUPPORTED = -3, /* valid but not handled by this build (brick != 4, sizes) */
+    PDM_E_DEVICE = -4       /* a kernel launch failed */
+} pdm_status;
+
+typedef enum { PDM_U8 = 1, PDM_U16 = 2 } pdm_dtype;
+
+typedef struct {
+    int32_t nx, ny, nz; /* voxels per axis, each >= 1; index ((z*ny)+y)*nx+x */
+    int32_t dtype;      /* pdm_dtype: bytes per voxel */
+    int32_t levels;     /* L: every voxel < L; u8: 1..256, u16: 1..65536 */
+    int32_t brick;      /* b; only 4 is supported (PDM_E_UNSUPPORTED otherwise) */
+} pdm_volume;
+
+typedef struct {
+    int32_t bx, by, bz; /* bricks per axis */
+    int64_t count;      /* G = bx*by*bz */
+} pdm_grid;
+
+/* Brick grid of a volume: Bx = ceil(nx/b), ... (Sec. 3.1).  Host only. */
+pdm_status pdm_grid_of(const pdm_volume* v, pdm_grid* out);
+
+/* Step 1 of the TF update (Sec. 3.1): S = { p : some intensity i in
+ * [h_bounds[p], h_bounds[p+1]-1] has h_alpha[i] != 0 }.  Every intensity of a
+ * partition is tested, present in the volume or not; NaN counts as non-zero.
+ * h_bounds: n+1 int32, h_bounds[0] = 0 < ... < h_bounds[n] = levels,
+ * n in [1, 256].  h_alpha: `levels` floats.  h_active: 4 words out, bit p of
+ * word p/64 set when p is in S.  Host only. */
+pdm_status pdm_active_set(const int32_t* h_bounds, int32_t n, const float* h_alpha,
+                          int32_t levels, uint64_t* h_active);
+
+/* Per-brick intensity minimum and maximum over the brick's voxels inside the
+ * volume; partial bricks on the far faces are clipped, never padded (Sec. 3.1
+ * block reduction).  d_volume: nx*ny*nz voxels of v->dtype.  d_bmin, d_bmax:
+ * G elements of v->dtype each.  d_range_err: nullable int32; if non-null it is
+ * set to 1 by the device when some voxel is >= levels (it is never cleared:
+ * zero it before the call). */
+pdm_status pdm_build_bricks(const pdm_volume* v, const void* d_volume, void* d_bmin,
+                            void* d_bmax, int32_t* d_range_err, hipStream_t stream);
+
+/* One-time initialisation (Sec. 3.1): for every partition p the POM
+ * (brick occupied when [bmin, bmax] meets [h_bounds[p], h_bounds[p+1]-1]) and
+ * its PDM, the exact chessboard distance in bricks to the nearest occupied
+ * brick of p, clamped at 255, and 255 everywhere when p occupies no brick.
+ * d_bmin/d_bmax: output of pdm_build_bricks.  d_pdms: n*G bytes, [p][brick].
+ * Equivalent to pdm_pom_distance_x followed by pdm_distance_yz(count = n). */
+pdm_status pdm_build_partitions(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                                const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                                hipStream_t stream);
+
+/* TF update (Sec. 3.1, both steps; Eq. 1): S from h_alpha as in
+ * pdm_active_set, then d_dist[c] = min over p in S of d_pdms[p*G + c]; 255
+ * when S is empty.  Only the PDMs of S are read.  h_active: nullable, 4 words
+ * out (the S mask). */
+pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32_t* h_bounds,
+                         int32_t n, const float* h_alpha, uint8_t* d_dist, uint64_t* h_active,
+                         hipStream_t stream);
+
+/* Plain method (Sec. 2 and Sec. 4.2): from the raw volume, the occupancy of
+ * every brick under the TF (occupied when some intensity i in the brick's
+ * [min, max] has h_alpha[i] != 0) and its clamped chessboard distance map D.
+ * h_alpha: v->levels floats, levels <= PDM_MAX_PLAIN_LEVELS.  d_dist: G bytes.
+ * Equivalent to pdm_plain_distance_x followed by pdm_distance_yz(count = 1).
+ * Voxels >= levels are a precondition violation (see pdm_build_bricks). */
+pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
+                              uint8_t* d_dist, hipStream_t stream);
+
+/* Phases, exposed so that each kernel can be timed on its own. */
+
+/* First phase of pdm_build_partitions: for every partition, the POM and the
+ * distance to the nearest occupied brick along x only (clamped at 255),
+ * written to d_pdms[p*G + c]. */
+pdm_status pdm_pom_distance_x(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                              const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                              hipStream_t stream);
+
+/* First phase of pdm_full_recompute: brick occupancy under the TF from the
+ * volume and the distance to the nearest occupied brick along x only. */
+pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
+                                uint8_t* d_dist, hipStream_t stream);
+
+/* Second phase of both: completes `count` stacked grids [count][G] in place
+ * from x-only distances to full chessboard distances with 1-D max-min passes
+ * along y and then z, g(i) = min over j of max(|i-j|, f(j)), clamped at 255. */
+pdm_status pdm_distance_yz(const pdm_volume* v, uint8_t* d_maps, int32_t count,
+                           hipStream_t stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* pdm_status_string(pdm_status s);
+
+/* Library version string (static storage). */
+const char* pdm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDM_H */

@@ -1,0 +1,92 @@
+"""Partitioned distance maps on MI355X (gfx950): a HIP library behind a C ABI.
+
+Paper: "Accelerating Transfer Function Update for Distance Map based Volume
+Rendering" (arXiv 2407.21552).  The C ABI is ``include/pdm.h``; ``_lib`` is
+its ctypes binding; ``Volume`` keeps one volume's device buffers together:
+
+    vol = Volume(t_volume_on_gpu, levels=256, bounds=uniform_bounds(256, 64))
+    vol.build()                      # brick [min,max] + PDMs (one-time init)
+    mask = vol.update_tf(alpha)      # D' (Eq. 1) into vol.dist
+    vol.full_recompute(alpha, out)   # plain method, D
+
+PyTorch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, active_set, build_bricks,
+                   build_partitions, distance_yz, full_recompute, grid_of, mask_to_list,
+                   plain_distance_x, pom_distance_x, tf_update, volume_desc)
+
+__all__ = ["Volume", "PdmError", "active_set", "build_bricks", "build_partitions", "distance_yz",
+           "full_recompute", "grid_of", "mask_to_list", "plain_distance_x", "pom_distance_x",
+           "tf_update", "volume_desc", "BRICK", "DIST_CAP", "MAX_PARTITIONS", "to_device",
+           "from_device"]
+
+
+def to_device(arr: np.ndarray, device="cuda"):
+    """Copy a uint8/uint16 numpy array to the GPU (uint16 travels as int16
+    bits; the library only sees bytes)."""
+    import torch
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.uint16:
+        a = a.view(np.int16)
+    return torch.from_numpy(a).to(device)
+
+
+def from_device(t, dtype=None) -> np.ndarray:
+    a = t.detach().cpu().numpy()
+    if dtype is not None and np.dtype(dtype) == np.uint16:
+        a = a.view(np.uint16)
+    return a
+
+
+class Volume:
+    """One volume resident on the GPU with its bricks, PDMs and output map.
+
+    t_volume: contiguous (nz, ny, nx) tensor of uint8, or int16 holding the
+    bits of uint16 intensities (dtype given by `voxel_dtype`)."""
+
+    def __init__(self, t_volume, levels: int, bounds, voxel_dtype=None):
+        import torch
+        if voxel_dtype is None:
+            voxel_dtype = np.uint8 if t_volume.dtype == torch.uint8 else np.uint16
+        self.voxel_dtype = np.dtype(voxel_dtype)
+        self.volume = t_volume
+        self.levels = int(levels)
+        self.bounds = np.ascontiguousarray(bounds, dtype=np.int32)
+        self.n = len(self.bounds) - 1
+        self.desc = volume_desc(t_volume.shape, self.voxel_dtype, levels)
+        self.bz, self.by, self.bx, self.G = grid_of(self.desc)
+        tdt = torch.uint8 if self.voxel_dtype.itemsize == 1 else torch.int16
+        dev = t_volume.device
+        self.bmin = torch.empty((self.bz, self.by, self.bx), dtype=tdt, device=dev)
+        self.bmax = torch.empty_like(self.bmin)
+        self.pdms = torch.empty((self.n, self.bz, self.by, self.bx), dtype=torch.uint8, device=dev)
+        self.dist = torch.empty((self.bz, self.by, self.bx), dtype=torch.uint8, device=dev)
+        self.range_err = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    @property
+    def pdm_bytes(self) -> int:
+        return self.n * self.G
+
+    def build(self, stream=None) -> None:
+        """One-time initialisation: brick [min,max], then every PDM."""
+        build_bricks(self.desc, self.volume, self.bmin, self.bmax, self.range_err, stream)
+        build_partitions(self.desc, self.bmin, self.bmax, self.bounds, self.pdms, stream)
+
+    def check_range(self) -> None:
+        """Synchronises; raises PdmError if some voxel was >= levels."""
+        if int(self.range_err.item()) != 0:
+            raise PdmError(_lib.PDM_E_RANGE, "volume holds a voxel >= levels")
+
+    def update_tf(self, alpha, out=None, stream=None) -> np.ndarray:
+        """D' for a new opacity table; returns the S mask."""
+        return tf_update(self.desc, self.pdms, self.bounds, alpha,
+                         self.dist if out is None else out, stream)
+
+    def full_recompute(self, alpha, out=None, stream=None) -> None:
+        """Plain method: D from the raw volume."""
+        full_recompute(self.desc, self.volume, alpha, self.dist if out is None else out, stream)

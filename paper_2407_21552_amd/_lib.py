@@ -1,0 +1,238 @@
+"""ctypes binding of libpdm (include/pdm.h): argument marshalling only.
+
+Every step of the path runs inside libpdm (host validation, the active set,
+the kernels).  This module checks that torch tensors have the dtype, size,
+device and layout the C ABI documents, passes their device pointers and
+torch's current HIP stream, and raises PdmError on a non-zero status.  It
+fails loudly when libpdm.so is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pdm.h")
+
+PDM_OK, PDM_E_INVAL, PDM_E_RANGE, PDM_E_UNSUPPORTED, PDM_E_DEVICE = 0, -1, -2, -3, -4
+PDM_U8, PDM_U16 = 1, 2
+BRICK = 4
+DIST_CAP = 255
+MAX_PARTITIONS = 256
+
+
+class PdmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("levels", ctypes.c_int32), ("brick", ctypes.c_int32)]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
+                ("count", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libpdm.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+        V = ctypes.POINTER(VolumeDesc)
+        L.pdm_grid_of.argtypes = [V, ctypes.POINTER(GridDesc)]
+        L.pdm_active_set.argtypes = [P, i32, P, i32, P]
+        L.pdm_build_bricks.argtypes = [V, P, P, P, P, P]
+        L.pdm_build_partitions.argtypes = [V, P, P, P, i32, P, P]
+        L.pdm_tf_update.argtypes = [V, P, P, i32, P, P, P, P]
+        L.pdm_full_recompute.argtypes = [V, P, P, P, P]
+        L.pdm_pom_distance_x.argtypes = [V, P, P, P, i32, P, P]
+        L.pdm_plain_distance_x.argtypes = [V, P, P, P, P]
+        L.pdm_distance_yz.argtypes = [V, P, i32, P]
+        for name in ("pdm_grid_of", "pdm_active_set", "pdm_build_bricks", "pdm_build_partitions",
+                     "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
+                     "pdm_plain_distance_x", "pdm_distance_yz"):
+            getattr(L, name).restype = st
+        L.pdm_status_string.argtypes = [st]
+        L.pdm_status_string.restype = ctypes.c_char_p
+        L.pdm_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Names of the functions include/pdm.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdm_[a-z_]+)\s*\(", text)))
+
+
+def status_string(code: int) -> str:
+    return lib().pdm_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return lib().pdm_version().decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != PDM_OK:
+        raise PdmError(code, what)
+
+
+# ------------------------------------------------------------- descriptors
+def volume_desc(shape_zyx, dtype, levels: int, brick: int = BRICK) -> VolumeDesc:
+    nz, ny, nx = (int(s) for s in shape_zyx)
+    code = {1: PDM_U8, 2: PDM_U16}[np.dtype(_np_dtype(dtype)).itemsize]
+    return VolumeDesc(nx, ny, nz, code, int(levels), int(brick))
+
+
+def _np_dtype(dtype):
+    try:
+        import torch
+        if isinstance(dtype, torch.dtype):
+            return {torch.uint8: np.uint8, torch.uint16: np.uint16, torch.int16: np.uint16}[dtype]
+    except ImportError:
+        pass
+    return np.dtype(dtype)
+
+
+def grid_of(desc: VolumeDesc):
+    """(Bz, By, Bx, G) of a volume descriptor."""
+    g = GridDesc()
+    _check(lib().pdm_grid_of(ctypes.byref(desc), ctypes.byref(g)), "pdm_grid_of")
+    return g.bz, g.by, g.bx, g.count
+
+
+def _bounds(bounds) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(bounds, dtype=np.int32))
+
+
+def _alpha(alpha, levels: int) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(alpha, dtype=np.float32))
+    if a.ndim != 1 or a.size != levels:
+        raise ValueError(f"alpha must hold {levels} float32 entries, got shape {a.shape}")
+    return a
+
+
+def _np_ptr(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def active_set(bounds, alpha, levels: int) -> np.ndarray:
+    """Step 1 of the TF update: the 4-word uint64 mask of S (host only)."""
+    b = _bounds(bounds)
+    a = _alpha(alpha, levels)
+    m = np.zeros(4, np.uint64)
+    _check(lib().pdm_active_set(_np_ptr(b), len(b) - 1, _np_ptr(a), int(levels), _np_ptr(m)),
+           "pdm_active_set")
+    return m
+
+
+def mask_to_list(mask, n: int):
+    return [p for p in range(n) if (int(mask[p >> 6]) >> (p & 63)) & 1]
+
+
+# ------------------------------------------------------------ tensor checks
+def _dev_ptr(t, nbytes: int, what: str) -> ctypes.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if t.numel() * t.element_size() != nbytes:
+        raise ValueError(f"{what}: expected {nbytes} bytes, got {t.numel() * t.element_size()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _vox_bytes(desc: VolumeDesc) -> int:
+    return desc.nx * desc.ny * desc.nz * desc.dtype
+
+
+# ------------------------------------------------------------- entry points
+def build_bricks(desc, volume, bmin, bmax, range_err=None, stream=None) -> None:
+    G = grid_of(desc)[3]
+    err = ctypes.c_void_p(0) if range_err is None else _dev_ptr(range_err, 4, "range_err")
+    _check(lib().pdm_build_bricks(ctypes.byref(desc), _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                  _dev_ptr(bmin, G * desc.dtype, "bmin"),
+                                  _dev_ptr(bmax, G * desc.dtype, "bmax"), err, _stream(stream)),
+           "pdm_build_bricks")
+
+
+def build_partitions(desc, bmin, bmax, bounds, pdms, stream=None) -> None:
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    _check(lib().pdm_build_partitions(ctypes.byref(desc), _dev_ptr(bmin, G * desc.dtype, "bmin"),
+                                      _dev_ptr(bmax, G * desc.dtype, "bmax"), _np_ptr(b), n,
+                                      _dev_ptr(pdms, n * G, "pdms"), _stream(stream)),
+           "pdm_build_partitions")
+
+
+def pom_distance_x(desc, bmin, bmax, bounds, pdms, stream=None) -> None:
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    _check(lib().pdm_pom_distance_x(ctypes.byref(desc), _dev_ptr(bmin, G * desc.dtype, "bmin"),
+                                    _dev_ptr(bmax, G * desc.dtype, "bmax"), _np_ptr(b), n,
+                                    _dev_ptr(pdms, n * G, "pdms"), _stream(stream)),
+           "pdm_pom_distance_x")
+
+
+def distance_yz(desc, maps, count: int, stream=None) -> None:
+    G = grid_of(desc)[3]
+    _check(lib().pdm_distance_yz(ctypes.byref(desc), _dev_ptr(maps, count * G, "maps"), int(count),
+                                 _stream(stream)), "pdm_distance_yz")
+
+
+def tf_update(desc, pdms, bounds, alpha, dist, stream=None) -> np.ndarray:
+    """D' into `dist`; returns the S mask."""
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    a = _alpha(alpha, desc.levels)
+    m = np.zeros(4, np.uint64)
+    _check(lib().pdm_tf_update(ctypes.byref(desc), _dev_ptr(pdms, n * G, "pdms"), _np_ptr(b), n,
+                               _np_ptr(a), _dev_ptr(dist, G, "dist"), _np_ptr(m), _stream(stream)),
+           "pdm_tf_update")
+    return m
+
+
+def full_recompute(desc, volume, alpha, dist, stream=None) -> None:
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_full_recompute(ctypes.byref(desc), _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                    _np_ptr(a), _dev_ptr(dist, G, "dist"), _stream(stream)),
+           "pdm_full_recompute")
+
+
+def plain_distance_x(desc, volume, alpha, dist, stream=None) -> None:
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_plain_distance_x(ctypes.byref(desc),
+                                      _dev_ptr(volume, _vox_bytes(desc), "volume"), _np_ptr(a),
+                                      _dev_ptr(dist, G, "dist"), _stream(stream)),
+           "pdm_plain_distance_x")

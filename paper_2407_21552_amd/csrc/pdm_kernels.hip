@@ -1,0 +1,665 @@
+// pdm_kernels.hip -- gfx950 kernels for partitioned distance maps.
+//
+// Paper: arXiv 2407.21552.  Sec. 3.1 defines the brick reduction (b = 4), the
+// partitioned occupancy maps (POMs), the partitioned distance maps (PDMs,
+// chessboard distance in bricks) and the update D' = min over p in S of PDM_p
+// (Eq. 1); Sec. 3.2 stores distances as uint8 clamped at 255; Sec. 2 and 4.2
+// describe the plain method (occupancy and distance map recomputed per TF).
+//
+// Everything here is integer byte work bound by HBM bandwidth or by the
+// per-line scans; there is no dense contraction, so no MFMA.
+//
+// Kernels
+//   k_bricks        volume -> per-brick [min,max]; one lane per 4 bricks in x
+//                   (16 voxels = one 16-byte load per voxel row for u8).
+//   k_pom_x         [min,max] -> for every partition, the POM and the distance
+//                   to the nearest occupied brick along x (wave ballots).
+//   k_plain_x       volume + TF -> occupancy and x distance (plain method).
+//   k_dist_axis     x distances -> full chessboard distances: 1-D max-min pass
+//                   along y or z, one lane per line, linear-time scan.
+//   k_combine       masked min over the active PDM streams, 16 bytes per lane.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdm_launch.h"
+
+namespace pdm {
+
+constexpr int kWave = 64;
+constexpr int kSegBricks = 4 * kWave;  // bricks of one x segment handled by a wave
+constexpr int kNone = 1 << 20;         // "no occupied brick": farther than any cap
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_min16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(us2, a),
+                                                                  __builtin_bit_cast(us2, b)));
+}
+__device__ __forceinline__ uint32_t pk_max16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(us2, a),
+                                                                  __builtin_bit_cast(us2, b)));
+}
+// bytes 0 and 2 of w in the two 16-bit halves
+__device__ __forceinline__ uint32_t even_bytes(uint32_t w) { return w & 0x00FF00FFu; }
+// bytes 1 and 3 of w in the two 16-bit halves
+__device__ __forceinline__ uint32_t odd_bytes(uint32_t w) {
+    return __builtin_amdgcn_perm(0u, w, 0x0c030c01u);
+}
+__device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
+__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Brick [min,max] of the 4 bricks x = 4q..4q+3 of brick row (bz, by):
+// voxels x in [16q, 16q+16), y in [4by, 4by+4), z in [4bz, 4bz+4), clipped to
+// the volume.  Results for bricks outside the grid are unspecified.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct QuadMinMax {
+    uint32_t mn[4], mx[4];
+};
+
+template <typename T>
+__device__ __forceinline__ QuadMinMax<T> quad_minmax(const T* __restrict__ vol, int nx, int ny,
+                                                     int nz, int q, int by, int bz, bool vec_ok) {
+    QuadMinMax<T> r;
+    const int x0 = 16 * q;
+    const int z0 = 4 * bz, y0 = 4 * by;
+    const int zn = min(4, nz - z0), yn = min(4, ny - y0);
+    if (vec_ok && x0 + 16 <= nx) {
+        if constexpr (sizeof(T) == 1) {
+            // even/odd byte lanes held as packed u16 pairs, one pair per brick
+            uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
+            for (int zz = 0; zz < zn; ++zz) {
+#pragma unroll
+                for (int yy = 0; yy < 4; ++yy) {
+                    if (yy < yn) {
+                        const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+                        const uint4 w = *reinterpret_cast<const uint4*>(vol + off);
+                        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
+                            mnE[k] = pk_min16(mnE[k], e);
+                            mnO[k] = pk_min16(mnO[k], o);
+                            mxE[k] = pk_max16(mxE[k], e);
+                            mxO[k] = pk_max16(mxO[k], o);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a = pk_min16(mnE[k], mnO[k]);
+                const uint32_t b = pk_max16(mxE[k], mxO[k]);
+                r.mn[k] = umin(lo16(a), hi16(a));
+                r.mx[k] = umax(lo16(b), hi16(b));
+            }
+        } else {
+            // u16: each 32-bit word holds 2 voxels; 2 words per brick row
+            uint32_t mn[4], mx[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
+            for (int zz = 0; zz < zn; ++zz) {
+#pragma unroll
+                for (int yy = 0; yy < 4; ++yy) {
+                    if (yy < yn) {
+                        const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+                        const uint4* p = reinterpret_cast<const uint4*>(vol + off);
+                        const uint4 a = p[0], b = p[1];
+                        const uint32_t ws[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
+                            mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
+                r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
+            }
+        }
+    } else {
+        // ragged or unaligned rows: one voxel at a time
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { r.mn[k] = 0xFFFFFFFFu; r.mx[k] = 0u; }
+        const int xn = min(16, nx - x0);
+        for (int zz = 0; zz < zn; ++zz)
+            for (int yy = 0; yy < yn; ++yy) {
+                const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int xx = 0; xx < 4; ++xx)
+                        if (4 * k + xx < xn) {
+                            const uint32_t val = vol[off + 4 * k + xx];
+                            r.mn[k] = umin(r.mn[k], val);
+                            r.mx[k] = umax(r.mx[k], val);
+                        }
+            }
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// k_bricks: one lane per 4 bricks along x.  Grid covers Qx*By*Bz lanes,
+// Qx = ceil(Bx/4), quad index fastest so neighbouring lanes read neighbouring
+// 16-byte chunks of the same voxel rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int nx, int ny, int nz,
+                                                int Bx, int By, int Bz, int Qx, T* __restrict__ bmin,
+                                                T* __restrict__ bmax, int levels,
+                                                int32_t* __restrict__ range_err, int vec_ok,
+                                                int store_vec) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)Qx * By * Bz;
+    if (t >= total) return;
+    const int q = (int)(t % Qx);
+    const int64_t row = t / Qx;
+    const int by = (int)(row % By), bz = (int)(row / By);
+    const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0);
+    const int64_t base = row * Bx + 4 * q;
+    const int nb = min(4, Bx - 4 * q);
+    if (range_err != nullptr) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nb) m = umax(m, r.mx[k]);
+        if (m >= (uint32_t)levels) *range_err = 1;
+    }
+    if (store_vec && nb == 4) {
+        if constexpr (sizeof(T) == 1) {
+            *reinterpret_cast<uint32_t*>(bmin + base) =
+                r.mn[0] | (r.mn[1] << 8) | (r.mn[2] << 16) | (r.mn[3] << 24);
+            *reinterpret_cast<uint32_t*>(bmax + base) =
+                r.mx[0] | (r.mx[1] << 8) | (r.mx[2] << 16) | (r.mx[3] << 24);
+        } else {
+            *reinterpret_cast<uint2*>(bmin + base) =
+                make_uint2(r.mn[0] | (r.mn[1] << 16), r.mn[2] | (r.mn[3] << 16));
+            *reinterpret_cast<uint2*>(bmax + base) =
+                make_uint2(r.mx[0] | (r.mx[1] << 16), r.mx[2] | (r.mx[3] << 16));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nb) {
+                bmin[base + k] = (T)r.mn[k];
+                bmax[base + k] = (T)r.mx[k];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Distances along x inside one wave.  Lane L holds the occupancy nibble `o`
+// of bricks xs+4L .. xs+4L+3 (bit k = brick xs+4L+k).  prev_last is the last
+// occupied brick left of the segment and next_first the first one right of it
+// (absolute x, or -kNone / +kNone).  Returns the 4 clamped distances packed
+// into bytes.  Must be called by the whole wave.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t x_distances(uint32_t o, int lane, int xs, int prev_last,
+                                                int next_first) {
+    const uint64_t any = __ballot(o != 0u);
+    const int hik = o ? 31 - __clz(o) : 0;
+    const int lok = o ? __ffs(o) - 1 : 0;
+    const uint64_t below = any & ((1ull << lane) - 1ull);
+    const uint64_t above = (lane == kWave - 1) ? 0ull : (any & (~0ull << (lane + 1)));
+    const int src_l = below ? 63 - __clzll((long long)below) : lane;
+    const int src_r = above ? __ffsll((unsigned long long)above) - 1 : lane;
+    const int hi_l = __shfl(hik, src_l, kWave);
+    const int lo_r = __shfl(lok, src_r, kWave);
+    const int left_lane = below ? xs + 4 * src_l + hi_l : prev_last;
+    const int right_lane = above ? xs + 4 * src_r + lo_r : next_first;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = xs + 4 * lane + k;
+        const uint32_t ml = o & ((2u << k) - 1u);
+        const uint32_t mr = o & (0xFu & ~((1u << k) - 1u));
+        const int lp = ml ? xs + 4 * lane + (31 - __clz(ml)) : left_lane;
+        const int rp = mr ? xs + 4 * lane + (__ffs(mr) - 1) : right_lane;
+        int d = min(x - lp, rp - x);
+        d = min(d, 255);
+        packed |= (uint32_t)d << (8 * k);
+    }
+    return packed;
+}
+
+// Position of the first / last occupied brick of a segment (wave-uniform).
+__device__ __forceinline__ int seg_first(uint32_t o, int xs) {
+    const uint64_t any = __ballot(o != 0u);
+    const int lok = o ? __ffs(o) - 1 : 0;
+    const int src = any ? __ffsll((unsigned long long)any) - 1 : 0;
+    const int v = __shfl(lok, src, kWave);
+    return any ? xs + 4 * src + v : kNone;
+}
+__device__ __forceinline__ int seg_last(uint32_t o, int xs) {
+    const uint64_t any = __ballot(o != 0u);
+    const int hik = o ? 31 - __clz(o) : 0;
+    const int src = any ? 63 - __clzll((long long)any) : 0;
+    const int v = __shfl(hik, src, kWave);
+    return any ? xs + 4 * src + v : -kNone;
+}
+
+__device__ __forceinline__ void store_quad(uint8_t* __restrict__ dst, int64_t idx, int nb,
+                                           uint32_t packed, bool vec) {
+    if (vec && nb == 4) {
+        *reinterpret_cast<uint32_t*>(dst + idx) = packed;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nb) dst[idx + k] = (uint8_t)(packed >> (8 * k));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_pom_x: one wave per brick row (bz, by); 4 waves per work-group.  For
+// every partition p: POM nibble from [min,max] (RANGE reading) and the x
+// distances, written to pdms[p*G + row*Bx + x].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_pom_x(const T* __restrict__ bmin,
+                                               const T* __restrict__ bmax, int Bx, int64_t rows,
+                                               Bounds bounds, int n, uint8_t* __restrict__ pdms,
+                                               int64_t G, int store_vec) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (row >= rows) return;  // wave-uniform
+    const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
+    const int64_t rbase = row * Bx;
+    if (nseg == 1) {
+        uint32_t mn[4], mx[4];
+        const int nb = max(0, min(4, Bx - 4 * lane));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            mn[k] = k < nb ? (uint32_t)bmin[rbase + 4 * lane + k] : 0xFFFFFFFFu;
+            mx[k] = k < nb ? (uint32_t)bmax[rbase + 4 * lane + k] : 0u;
+        }
+        for (int p = 0; p < n; ++p) {
+            const uint32_t lo = (uint32_t)bounds.b[p], hi = (uint32_t)bounds.b[p + 1] - 1u;
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
+            if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase + 4 * lane, nb, packed, store_vec);
+        }
+        return;
+    }
+    // long rows: segments of 256 bricks; only the neighbouring segments can
+    // hold a brick within the cap
+    auto nibble = [&](int seg, uint32_t lo, uint32_t hi) -> uint32_t {
+        const int x = seg * kSegBricks + 4 * lane;
+        uint32_t o = 0;
+        for (int k = 0; k < 4; ++k)
+            if (x + k < Bx) {
+                const uint32_t a = bmin[rbase + x + k], b = bmax[rbase + x + k];
+                o |= (a <= hi && b >= lo) ? (1u << k) : 0u;
+            }
+        return o;
+    };
+    for (int p = 0; p < n; ++p) {
+        const uint32_t lo = (uint32_t)bounds.b[p], hi = (uint32_t)bounds.b[p + 1] - 1u;
+        int prev_last = -kNone;
+        uint32_t cur = nibble(0, lo, hi);
+        for (int s = 0; s < nseg; ++s) {
+            const int xs = s * kSegBricks;
+            const uint32_t nxt = (s + 1 < nseg) ? nibble(s + 1, lo, hi) : 0u;
+            const int next_first = (s + 1 < nseg) ? seg_first(nxt, xs + kSegBricks) : kNone;
+            const uint32_t packed = x_distances(cur, lane, xs, prev_last, next_first);
+            const int nb = max(0, min(4, Bx - xs - 4 * lane));
+            if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase + xs + 4 * lane, nb, packed, store_vec);
+            prev_last = seg_last(cur, xs);
+            cur = nxt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain method, phase 1.  One wave per brick row; each lane reduces its 4
+// bricks from the volume, tests [min,max] against the non-zero opacity bitmap
+// and the wave computes x distances.  The bitmap test uses per-word prefix
+// counts in LDS: any set bit in [lo,hi].
+// ---------------------------------------------------------------------------
+constexpr int kMaxSegs = PDM_PLAIN_MAX_SEGS;
+
+__device__ __forceinline__ bool any_bit(const uint32_t* __restrict__ words,
+                                        const uint16_t* __restrict__ pre, uint32_t lo, uint32_t hi) {
+    const uint32_t wl = lo >> 5, wh = hi >> 5;
+    const uint32_t ml = ~0u << (lo & 31u);
+    const uint32_t mh = (hi & 31u) == 31u ? ~0u : ((2u << (hi & 31u)) - 1u);
+    if (wl == wh) return (words[wl] & ml & mh) != 0u;
+    if ((words[wl] & ml) != 0u || (words[wh] & mh) != 0u) return true;
+    return pre[wh] != pre[wl + 1];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int nx, int ny, int nz,
+                                                 int Bx, int By, int64_t rows, AlphaBits bits,
+                                                 int nwords, int levels, uint8_t* __restrict__ dist,
+                                                 int vec_ok, int store_vec) {
+    __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
+    __shared__ uint16_t s_pre[PDM_ALPHA_WORDS + 1];
+    __shared__ uint8_t s_nib[4][kMaxSegs][kWave];
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < nwords; ++i) {
+            s_pre[i] = (uint16_t)acc;
+            acc += __popc(s_words[i]);
+        }
+        s_pre[nwords] = (uint16_t)acc;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    if (row >= rows) return;  // wave-uniform, after the last barrier
+    const int by = (int)(row % By), bz = (int)(row / By);
+    const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
+    const int64_t rbase = row * Bx;
+    for (int s = 0; s < nseg; ++s) {
+        const int q = s * kWave + lane;  // quad index within the row
+        uint32_t o = 0;
+        if (4 * q < Bx) {
+            const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0);
+            const int nb = min(4, Bx - 4 * q);
+            // voxels >= levels break the precondition; clamping keeps the
+            // bitmap lookups inside the table
+            const uint32_t top = (uint32_t)levels - 1u;
+            for (int k = 0; k < 4; ++k)
+                if (k < nb && any_bit(s_words, s_pre, umin(r.mn[k], top), umin(r.mx[k], top)))
+                    o |= 1u << k;
+        }
+        s_nib[wv][s][lane] = (uint8_t)o;
+    }
+    // the wave reads back only its own entries (written by its own lanes)
+    __builtin_amdgcn_wave_barrier();
+    for (int s = 0; s < nseg; ++s) {
+        const int xs = s * kSegBricks;
+        const uint32_t cur = s_nib[wv][s][lane];
+        const int prev_last = s > 0 ? seg_last(s_nib[wv][s - 1][lane], xs - kSegBricks) : -kNone;
+        const int next_first = s + 1 < nseg ? seg_first(s_nib[wv][s + 1][lane], xs + kSegBricks) : kNone;
+        const uint32_t packed = x_distances(cur, lane, xs, prev_last, next_first);
+        const int nb = max(0, min(4, Bx - xs - 4 * lane));
+        if (nb > 0) store_quad(dist, rbase + xs + 4 * lane, nb, packed, store_vec);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_dist_axis: 1-D max-min pass g(i) = min_j max(|i-j|, f(j)), in place, for
+// lines along y (stride Bx) or z (stride Bx*By).  One lane per line, x
+// fastest so a wave touches 64 consecutive bytes per step.
+//
+// The pass is a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
+// followed by the same pass backwards over F, which yields g exactly (a
+// candidate j > i reaches i only through the backward pass, j <= i through
+// the forward one).  The one-sided pass runs in one sweep: keep v = F(i-1)
+// and W = the latest j attaining it (max(i-1-j, f(j)) <= v).  Then F(i) is
+// min(f(i), X) with X = v if i-W <= v, else v+1; in the second case the new
+// latest witness is W or the latest j in the window with f(j) = v+1, found in
+// a per-lane table last[w] = latest position with value w.  Table entries
+// start at 0; a real position 0 is never needed because an accepted entry
+// must exceed W >= 0.
+// ---------------------------------------------------------------------------
+// The per-lane tables of a work-group: 256 rows (one per value w) of TPB
+// entries (one per lane).  The lane's column is XOR-swizzled by w so that
+// lanes looking up different values hit different LDS banks; 64 KiB total.
+template <typename P, int TPB>
+__device__ __forceinline__ int tbl_index(int w, int tid) {
+    constexpr int kScale = 4 / (int)sizeof(P);
+    return w * TPB + (tid ^ ((w * kScale) & (TPB - 1)));
+}
+
+template <typename P, int TPB>
+__device__ __forceinline__ void clear_table(P* tbl) {
+    constexpr int kBytes = 256 * TPB * (int)sizeof(P);
+    uint4* t4 = reinterpret_cast<uint4*>(tbl);
+    for (int i = threadIdx.x; i < kBytes / 16; i += TPB) t4[i] = make_uint4(0, 0, 0, 0);
+}
+
+template <typename P, int TPB, int CH>
+__device__ __forceinline__ void one_sided(uint8_t* __restrict__ line, int64_t stride, int m,
+                                          bool reverse, bool active, P* __restrict__ tbl) {
+    const int tid = threadIdx.x;
+    int v = 0, W = 0;
+    for (int c = 0; c < m; c += CH) {
+        uint32_t f[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = c + k;
+            const int64_t pos = reverse ? (int64_t)(m - 1 - i) : (int64_t)i;
+            f[k] = (active && i < m) ? (uint32_t)line[pos * stride] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = c + k;
+            if (i < m) {
+                const int fi = (int)f[k];
+                if (i == 0) {
+                    v = fi;
+                    W = 0;
+                } else {
+                    const int t = (int)tbl[tbl_index<P, TPB>(min(v + 1, 255), tid)];
+                    const bool adv = (i - W) > v;
+                    const int X = v + (adv ? 1 : 0);
+                    if (fi <= X) {
+                        v = fi;
+                        W = i;
+                    } else if (adv) {
+                        v = X;
+                        W = max(W, t);
+                    }
+                }
+                tbl[tbl_index<P, TPB>(fi, tid)] = (P)i;
+                f[k] = (uint32_t)v;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = c + k;
+            const int64_t pos = reverse ? (int64_t)(m - 1 - i) : (int64_t)i;
+            if (active && i < m) line[pos * stride] = (uint8_t)f[k];
+        }
+    }
+}
+
+template <typename P, int TPB>
+__global__ void __launch_bounds__(TPB) k_dist_axis(uint8_t* __restrict__ maps, int64_t lines,
+                                                   int Bx, int inner, int64_t plane,
+                                                   int64_t stride, int m, int64_t G) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    P* tbl = reinterpret_cast<P*>(s_raw);
+    const int64_t l = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const bool active = l < lines;
+    uint8_t* line = maps;
+    if (active) {
+        // line l: x fastest, then the other in-grid axis (`inner` values with
+        // step `plane`), then the grid index
+        const int64_t x = l % Bx;
+        const int64_t r = l / Bx;
+        const int64_t a = r % inner;
+        const int64_t g = r / inner;
+        line = maps + g * G + a * plane + x;
+    }
+    clear_table<P, TPB>(tbl);
+    __syncthreads();
+    one_sided<P, TPB, 16>(line, stride, m, false, active, tbl);
+    __syncthreads();
+    clear_table<P, TPB>(tbl);
+    __syncthreads();
+    one_sided<P, TPB, 16>(line, stride, m, true, active, tbl);
+}
+
+// ---------------------------------------------------------------------------
+// k_combine: D'[c] = min over the listed partitions of pdms[p*G + c].  Each
+// lane owns 16 consecutive bricks (VEC = 16), 4 (VEC = 4) or 1 (VEC = 1),
+// keeping the running minimum as even/odd byte pairs in packed u16 lanes.
+// An empty list writes 255.
+// ---------------------------------------------------------------------------
+template <int VEC>
+__global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdms, int64_t G,
+                                                 ActiveList act, uint8_t* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = act.count;
+    if constexpr (VEC == 16) {
+        const int64_t off = t * 16;
+        if (off >= G) return;
+        uint32_t e[4], o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = o[k] = 0x00FF00FFu;
+        int j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            uint4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                q[u] = *reinterpret_cast<const uint4*>(pdms + (int64_t)act.p[j + u] * G + off);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    e[k] = pk_min16(e[k], even_bytes(w[k]));
+                    o[k] = pk_min16(o[k], odd_bytes(w[k]));
+                }
+            }
+        }
+        for (; j < cnt; ++j) {
+            const uint4 q = *reinterpret_cast<const uint4*>(pdms + (int64_t)act.p[j] * G + off);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                e[k] = pk_min16(e[k], even_bytes(w[k]));
+                o[k] = pk_min16(o[k], odd_bytes(w[k]));
+            }
+        }
+        uint4 r;
+        r.x = e[0] | (o[0] << 8);
+        r.y = e[1] | (o[1] << 8);
+        r.z = e[2] | (o[2] << 8);
+        r.w = e[3] | (o[3] << 8);
+        *reinterpret_cast<uint4*>(out + off) = r;
+    } else if constexpr (VEC == 4) {
+        const int64_t off = t * 4;
+        if (off >= G) return;
+        uint32_t e = 0x00FF00FFu, o = 0x00FF00FFu;
+        for (int j = 0; j < cnt; ++j) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(pdms + (int64_t)act.p[j] * G + off);
+            e = pk_min16(e, even_bytes(w));
+            o = pk_min16(o, odd_bytes(w));
+        }
+        *reinterpret_cast<uint32_t*>(out + off) = e | (o << 8);
+    } else {
+        if (t >= G) return;
+        uint32_t m = 255u;
+        for (int j = 0; j < cnt; ++j) m = umin(m, (uint32_t)pdms[(int64_t)act.p[j] * G + t]);
+        out[t] = (uint8_t)m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side).  Shapes are validated by the caller.
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t threads, int tpb) {
+    return (unsigned)((threads + tpb - 1) / tpb);
+}
+
+hipError_t launch_bricks(const BrickArgs& a, hipStream_t s) {
+    const int Qx = (a.Bx + 3) / 4;
+    const int64_t thr = (int64_t)Qx * a.By * a.Bz;
+    const unsigned nb = blocks_for(thr, 256);
+    if (a.bytes == 1)
+        k_bricks<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
+                                             a.Bz, Qx, (uint8_t*)a.bmin, (uint8_t*)a.bmax,
+                                             a.levels, a.range_err, a.vec_ok, a.store_vec);
+    else
+        k_bricks<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                              a.By, a.Bz, Qx, (uint16_t*)a.bmin,
+                                              (uint16_t*)a.bmax, a.levels, a.range_err, a.vec_ok,
+                                              a.store_vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s) {
+    const int64_t rows = (int64_t)a.By * a.Bz;
+    const unsigned nb = blocks_for(rows, 4);
+    if (a.bytes == 1)
+        k_pom_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.bmin, (const uint8_t*)a.bmax, a.Bx,
+                                            rows, b, a.n, a.pdms, a.G, a.store_vec);
+    else
+        k_pom_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.bmin, (const uint16_t*)a.bmax,
+                                             a.Bx, rows, b, a.n, a.pdms, a.G, a.store_vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s) {
+    const int64_t rows = (int64_t)a.By * a.Bz;
+    const unsigned nb = blocks_for(rows, 4);
+    if (a.bytes == 1)
+        k_plain_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
+                                              rows, bits, a.nwords, a.levels, a.dist, a.vec_ok,
+                                              a.store_vec);
+    else
+        k_plain_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                               a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                               a.vec_ok, a.store_vec);
+    return hipGetLastError();
+}
+
+template <typename P, int TPB>
+static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, int axis,
+                              hipStream_t s) {
+    const int64_t G = (int64_t)Bx * By * Bz;
+    int64_t lines, plane, stride;
+    int inner, m;
+    if (axis == 1) {  // along y: lines (g, z, x)
+        lines = (int64_t)count * Bx * Bz;
+        inner = Bz;
+        plane = (int64_t)Bx * By;
+        stride = Bx;
+        m = By;
+    } else {  // along z: lines (g, y, x)
+        lines = (int64_t)count * Bx * By;
+        inner = By;
+        plane = Bx;
+        stride = (int64_t)Bx * By;
+        m = Bz;
+    }
+    const size_t lds = (size_t)256 * TPB * sizeof(P);
+    k_dist_axis<P, TPB><<<blocks_for(lines, TPB), TPB, lds, s>>>(maps, lines, Bx, inner, plane,
+                                                                 stride, m, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s) {
+    hipError_t e;
+    for (int axis = 1; axis <= 2; ++axis) {
+        const int m = axis == 1 ? By : Bz;
+        if (m == 1) continue;  // a line of one brick is unchanged
+        if (m <= 256)
+            e = launch_axis<uint8_t, 256>(maps, count, Bx, By, Bz, axis, s);
+        else
+            e = launch_axis<uint16_t, 128>(maps, count, Bx, By, Bz, axis, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
+                          int vec, hipStream_t s) {
+    if (vec == 16)
+        k_combine<16><<<blocks_for((G + 15) / 16, 256), 256, 0, s>>>(pdms, G, act, out);
+    else if (vec == 4)
+        k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(pdms, G, act, out);
+    else
+        k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(pdms, G, act, out);
+    return hipGetLastError();
+}
+
+}  // namespace pdm

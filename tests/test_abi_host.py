@@ -1,0 +1,133 @@
+"""The C ABI on the host: the library loads, exports every function the header
+declares, and rejects invalid arguments before any device work (so these run
+without a GPU).  Also checks the host-side active set (step 1 of the update,
+Sec. 3.1) against the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2407_21552_amd import _lib as L
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = L.header_symbols()
+    assert {"pdm_build_bricks", "pdm_build_partitions", "pdm_tf_update",
+            "pdm_full_recompute"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert "gfx950" in L.version()
+
+
+def test_status_strings(lib):
+    assert L.status_string(0) == "ok"
+    for c in (-1, -2, -3, -4):
+        assert L.status_string(c) not in ("ok", "unknown status")
+    assert L.status_string(7) == "unknown status"
+
+
+def desc(nx=64, ny=64, nz=64, dtype=1, levels=256, brick=4):
+    return L.VolumeDesc(nx, ny, nz, dtype, levels, brick)
+
+
+@pytest.mark.parametrize("shape,grid", [((64, 64, 64), (16, 16, 16, 4096)),
+                                        ((795, 1024, 1024), (199, 256, 256, 13041664)),
+                                        ((460, 512, 512), (115, 128, 128, 1884160)),
+                                        ((1, 1, 1), (1, 1, 1, 1)), ((5, 6, 9), (2, 2, 3, 12))])
+def test_grid_of(shape, grid):
+    assert L.grid_of(L.volume_desc(shape, np.uint8, 256)) == grid
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), L.PDM_E_INVAL), (dict(ny=-3), L.PDM_E_INVAL), (dict(dtype=3), L.PDM_E_INVAL),
+    (dict(levels=0), L.PDM_E_INVAL), (dict(levels=257), L.PDM_E_INVAL),
+    (dict(dtype=2, levels=65537), L.PDM_E_INVAL), (dict(brick=0), L.PDM_E_INVAL),
+    (dict(brick=8), L.PDM_E_UNSUPPORTED), (dict(nx=4 * 16385), L.PDM_E_UNSUPPORTED),
+    (dict(nz=4 * 65536), L.PDM_E_UNSUPPORTED)])
+def test_grid_of_rejects(kw, code):
+    with pytest.raises(L.PdmError) as e:
+        L.grid_of(desc(**kw))
+    assert e.value.code == code
+
+
+NULL = ctypes.c_void_p(0)
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def _b(arr):
+    a = np.ascontiguousarray(arr, np.int32)
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def test_null_pointers_rejected(lib):
+    d = desc()
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    alpha = np.zeros(256, np.float32)
+    pa = ctypes.c_void_p(alpha.ctypes.data)
+    r = ctypes.byref
+    assert lib.pdm_build_bricks(r(d), NULL, FAKE, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_bricks(r(d), FAKE, NULL, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_partitions(r(d), FAKE, FAKE, pb, 8, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_partitions(r(d), FAKE, FAKE, NULL, 8, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_tf_update(r(d), NULL, pb, 8, pa, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_tf_update(r(d), FAKE, pb, 8, NULL, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute(r(d), FAKE, pa, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute(r(d), FAKE, NULL, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_distance_yz(r(d), NULL, 1, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_distance_yz(r(d), FAKE, 0, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_distance_yz(r(d), FAKE, 257, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_bricks(None, FAKE, FAKE, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_grid_of(r(d), None) == L.PDM_E_INVAL
+
+
+@pytest.mark.parametrize("bounds,n", [
+    ([0, 128, 128, 256], 3), ([1, 128, 256], 2), ([0, 128, 255], 2), ([0, 300], 1),
+    ([0, 256], 0), (list(range(0, 258)), 257)])
+def test_bad_bounds_rejected_before_launch(lib, bounds, n):
+    d = desc()
+    bnd, pb = _b(bounds)
+    alpha = np.ones(256, np.float32)
+    pa = ctypes.c_void_p(alpha.ctypes.data)
+    r = ctypes.byref
+    assert lib.pdm_build_partitions(r(d), FAKE, FAKE, pb, n, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_pom_distance_x(r(d), FAKE, FAKE, pb, n, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_tf_update(r(d), FAKE, pb, n, pa, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    m = np.zeros(4, np.uint64)
+    assert lib.pdm_active_set(pb, n, pa, 256, ctypes.c_void_p(m.ctypes.data)) == L.PDM_E_INVAL
+
+
+def test_plain_method_rejects_too_many_levels(lib):
+    d = desc(dtype=2, levels=16385)
+    alpha = np.ones(16385, np.float32)
+    assert lib.pdm_full_recompute(ctypes.byref(d), FAKE, ctypes.c_void_p(alpha.ctypes.data),
+                                  FAKE, NULL) == L.PDM_E_UNSUPPORTED
+
+
+def test_active_set_matches_oracle(orc):
+    rng = np.random.default_rng(3)
+    for L_, n in ((256, 8), (256, 64), (4096, 32), (256, 256), (8, 4), (4096, 1)):
+        bounds = W.uniform_bounds(L_, n)
+        for _ in range(20):
+            alpha = W.trapezoid_tf(L_, int(rng.integers(1, 5)), rng) if L_ >= 32 else \
+                (rng.random(L_) < 0.4).astype(np.float32)
+            np.testing.assert_array_equal(L.active_set(bounds, alpha, L_),
+                                          orc.active(bounds, alpha, L_))
+    # non-uniform borders, NaN and negative opacities
+    bounds = W.rhomin_bounds(256, 32, 3)
+    a = np.zeros(256, np.float32)
+    a[2] = np.nan
+    a[200] = -1.0
+    np.testing.assert_array_equal(L.active_set(bounds, a, 256), orc.active(bounds, a, 256))
+    assert L.mask_to_list(L.active_set(bounds, a, 256), 32) == \
+        orc.active_list(orc.active(bounds, a, 256), 32)
+
+
+def test_binding_rejects_wrong_alpha_length():
+    with pytest.raises(ValueError):
+        L.active_set(W.uniform_bounds(256, 8), np.zeros(255, np.float32), 256)

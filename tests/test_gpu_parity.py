@@ -1,0 +1,199 @@
+"""GPU parity: every output of the HIP path against the CPU oracle, bit-exact.
+
+Distances, brick summaries and active sets are integers, so the tolerance is
+zero.  Inputs are seeded and synthetic (workloads), shaped to span several
+work-groups and waves with ragged tails: dims not divisible by 4 or 16, rows
+longer than one 256-brick wave segment, y/z lines longer than 256 bricks
+(the 255 cap and the wide scan table), unaligned sizes for the vector paths.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdm():
+    import torch
+    import paper_2407_21552_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pkg._lib.lib()
+    return pkg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def blocky(shape, dtype, levels, seed, keep=0.15, cell=3):
+    """Piecewise-constant volume: many distinct brick intervals."""
+    rng = np.random.default_rng(seed)
+    cz, cy, cx = [(s + cell - 1) // cell for s in shape]
+    cells = rng.integers(0, levels, size=(cz, cy, cx))
+    cells = np.where(rng.random((cz, cy, cx)) < keep, cells, 0)
+    v = np.repeat(np.repeat(np.repeat(cells, cell, 0), cell, 1), cell, 2)
+    return np.ascontiguousarray(v[:shape[0], :shape[1], :shape[2]]).astype(dtype)
+
+
+def run_all(pdm, orc, vol, levels, bounds, alphas, label):
+    """Build on the GPU, apply every alpha both ways, compare everything."""
+    import torch
+    say(f"[case] {label}: shape={vol.shape} dtype={vol.dtype} L={levels} n={len(bounds) - 1}")
+    v = pdm.Volume(pdm.to_device(vol), levels, bounds, voxel_dtype=vol.dtype)
+    v.build()
+    torch.cuda.synchronize()
+    bmin, bmax = orc.bricks(vol)
+    np.testing.assert_array_equal(pdm.from_device(v.bmin, vol.dtype), bmin)
+    np.testing.assert_array_equal(pdm.from_device(v.bmax, vol.dtype), bmax)
+    want = orc.pdms(vol, bounds, levels, brick_minmax=(bmin, bmax))
+    np.testing.assert_array_equal(pdm.from_device(v.pdms), want)
+    d = torch.empty_like(v.dist)
+    for k, alpha in enumerate(alphas):
+        mask = v.update_tf(alpha)
+        if levels <= 16384:
+            v.full_recompute(alpha, out=d)
+        torch.cuda.synchronize()
+        dp, m = orc.tf_update(want, bounds, alpha, levels)
+        np.testing.assert_array_equal(mask, m)
+        np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"D' tf {k}")
+        if levels <= 16384:
+            np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, levels),
+                                          err_msg=f"D tf {k}")
+    return v
+
+
+def tfs(levels, count, seed, ramps=(1, 4)):
+    rng = np.random.default_rng(seed)
+    out = [W.trapezoid_tf(levels, int(rng.integers(ramps[0], ramps[1] + 1)), rng)
+           for _ in range(count)]
+    out.append(np.zeros(levels, np.float32))      # S empty
+    out.append(np.ones(levels, np.float32))       # every intensity opaque
+    return out
+
+
+def test_config1_full(pdm, orc):
+    cfg = W.config_info("c1")
+    vol = W.make_volume("c1")
+    alphas = W.make_tfs("c1") + tfs(256, 20, 77)
+    run_all(pdm, orc, vol, 256, W.uniform_bounds(256, cfg["n"]), alphas, "c1 64^3 u8")
+
+
+SHAPES = [
+    # (shape zyx, dtype, levels, n, label)
+    ((1, 1, 1), np.uint8, 256, 4, "single voxel"),
+    ((3, 5, 7), np.uint8, 256, 8, "one partial brick per axis"),
+    ((17, 9, 13), np.uint8, 256, 16, "ragged u8"),
+    ((23, 18, 30), np.uint16, 4096, 32, "ragged u16 12-bit"),
+    ((40, 36, 64), np.uint8, 256, 256, "one partition per level"),
+    ((12, 20, 64), np.uint16, 65536, 7, "u16 full range, uneven partitions"),
+    ((9, 14, 1030), np.uint8, 256, 8, "x rows over one wave segment"),
+    ((6, 5, 1100), np.uint16, 4096, 5, "u16 x rows over one segment"),
+    ((3, 1030, 6), np.uint8, 256, 3, "y lines over 256 bricks"),
+    ((1100, 2, 3), np.uint8, 256, 2, "z lines over 256 bricks"),
+    ((64, 64, 68), np.uint8, 256, 8, "x not a multiple of 16"),
+    ((20, 24, 40), np.uint8, 256, 1, "one partition"),
+]
+
+
+@pytest.mark.parametrize("shape,dtype,levels,n,label", SHAPES, ids=[s[-1] for s in SHAPES])
+def test_odd_shapes(pdm, orc, shape, dtype, levels, n, label):
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + n)
+    bounds = W.uniform_bounds(levels, n)
+    run_all(pdm, orc, vol, levels, bounds, tfs(levels, 6, sum(shape)), label)
+
+
+def test_capped_lines_closed_form(pdm, orc):
+    """A single occupied brick at one end of 1x1xN and Nx1x1 grids: the
+    distance along the line is min(k, 255)."""
+    import torch
+    for shape in ((1, 1, 4 * 300), (4 * 300, 1, 1), (1, 4 * 300, 1)):
+        say(f"[case] capped line {shape}")
+        vol = np.zeros(shape, np.uint8)
+        vol.reshape(-1)[0] = 200
+        v = pdm.Volume(pdm.to_device(vol), 256, W.uniform_bounds(256, 2))
+        v.build()
+        alpha = np.zeros(256, np.float32)
+        alpha[200] = 1.0
+        v.update_tf(alpha)
+        d = torch.empty_like(v.dist)
+        v.full_recompute(alpha, out=d)
+        torch.cuda.synchronize()
+        want = np.minimum(np.arange(300), 255).astype(np.uint8)
+        # partition 1 holds only the first brick; partition 0 holds every brick
+        np.testing.assert_array_equal(pdm.from_device(v.pdms[1]).reshape(-1), want)
+        assert (pdm.from_device(v.pdms[0]) == 0).all()
+        np.testing.assert_array_equal(pdm.from_device(d).reshape(-1), want)
+        # alpha non-zero only at 200: S = {1}, and D' = D
+        np.testing.assert_array_equal(pdm.from_device(v.dist).reshape(-1), want)
+
+
+def test_rhomin_partition(pdm, orc):
+    vol = W.make_volume("c1")
+    bounds = W.rhomin_bounds(256, 16, 2)
+    run_all(pdm, orc, vol, 256, bounds, tfs(256, 8, 5), "rho_min partition")
+
+
+def test_deterministic_and_no_out_of_bounds_writes(pdm, orc):
+    """Outputs written into the middle of guarded buffers: guard bytes stay
+    untouched and two runs give identical bytes."""
+    import torch
+    vol = blocky((37, 29, 45), np.uint8, 256, seed=9)
+    bounds = W.uniform_bounds(256, 8)
+    desc = pdm.volume_desc(vol.shape, np.uint8, 256)
+    bz, by, bx, G = pdm.grid_of(desc)
+    n = 8
+    guard = 4096
+    dvol = pdm.to_device(vol)
+
+    def guarded(nbytes):
+        t = torch.full((nbytes + 2 * guard,), 0xA5, dtype=torch.uint8, device="cuda")
+        return t, t[guard:guard + nbytes]
+
+    outs = []
+    for rep in range(2):
+        say(f"[case] guarded run {rep}")
+        gmin, bmin = guarded(G)
+        gmax, bmax = guarded(G)
+        gp, pd = guarded(n * G)
+        gd, dist = guarded(G)
+        gf, full = guarded(G)
+        pdm.build_bricks(desc, dvol, bmin, bmax)
+        pdm.build_partitions(desc, bmin, bmax, bounds, pd)
+        alpha = W.make_tfs("c1")[0]
+        pdm.tf_update(desc, pd, bounds, alpha, dist)
+        pdm.full_recompute(desc, dvol, alpha, full)
+        torch.cuda.synchronize()
+        for g in (gmin, gmax, gp, gd, gf):
+            h = g.cpu().numpy()
+            assert (h[:guard] == 0xA5).all() and (h[-guard:] == 0xA5).all()
+        outs.append([t.cpu().numpy().copy() for t in (bmin, bmax, pd, dist, full)])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_range_error_flag(pdm, orc):
+    import torch
+    vol = np.full((8, 8, 8), 100, np.uint16)
+    v = pdm.Volume(pdm.to_device(vol), 4096, W.uniform_bounds(4096, 4), voxel_dtype=np.uint16)
+    v.build()
+    v.check_range()                                  # clean volume: no error
+    vol[3, 5, 7] = 5000
+    v2 = pdm.Volume(pdm.to_device(vol), 4096, W.uniform_bounds(4096, 4), voxel_dtype=np.uint16)
+    v2.build()
+    torch.cuda.synchronize()
+    with pytest.raises(pdm.PdmError):
+        v2.check_range()
+
+
+def test_invalid_arguments_raise(pdm):
+    import torch
+    vol = torch.zeros((8, 8, 8), dtype=torch.uint8, device="cuda")
+    with pytest.raises(pdm.PdmError):
+        pdm.Volume(vol, 256, [0, 100, 100, 256]).build()
+    v = pdm.Volume(vol, 256, W.uniform_bounds(256, 4))
+    with pytest.raises(ValueError):
+        v.update_tf(np.zeros(100, np.float32))
+    with pytest.raises(ValueError):
+        pdm.tf_update(v.desc, v.pdms[:2], v.bounds, np.zeros(256, np.float32), v.dist)
