@@ -1,0 +1,300 @@
+"""Benchmark: TF update with partitioned distance maps vs full recompute.
+
+Workload (default): tube-tree volume 1024x1024x795 uint8, bricks 4^3
+(256x256x199 grid), 64 uniform partitions, the sequence of 200 random TFs
+(1-3 trapezoid ramps).  One step is one pass of the whole path over that
+input with the volume already resident in HBM:
+
+  brick [min,max] -> 64 PDMs (one-time initialisation, Sec. 3.1)
+  for each of the 200 TFs:
+      TF update  (active set + Eq. 1 min-combine)  -> D'
+      plain method (occupancy from the volume + distance map) -> D
+
+`value` is the whole step's algorithmic bytes divided by its wall time
+(GB/s).  Per-call durations come from HIP events recorded on the stream the
+library launches on; `roofline` is reported for the kernel that takes most of
+the step (the plain method's occupancy pass over the volume) and, as
+`roofline_tf_update`, for the min-combine kernel.  `cpu_baseline` is the CPU
+oracle timed on a slab of the same volume (see `cpu_baseline()`).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
+                       [--no-cpu-baseline] [--calib-copy-mib M]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2407_21552_amd", "csrc", "pdm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tube_tree_1024x1024x795.json")
+
+# paper's numbers (RTX 4090, OpenGL), kingsnake 1024x1024x795, 64 partitions
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA RTX 4090 (paper, Table 1)",
+    "dataset": "kingsnake 1024x1024x795, 64 partitions, TF1-TF6",
+    "pdm_update_ms": [1.97, 1.99, 1.23, 1.23, 1.68, 1.26],
+    "full_recompute_ms": [9.63, 7.28, 21.40, 14.59, 15.28, 9.76],
+    "init_ms": 913.7,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch measured with rocprofv3 counters, valid only for
+    the kernel source they were taken on."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return rec
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+def cpu_baseline(vol, bounds, alphas, levels, step_bytes_fn, slab_z=256, tfs=20):
+    """The CPU oracle (as it stands) on a bounded sample: the first `slab_z`
+    z-slices of the volume, the full build plus `tfs` TFs through both the
+    update and the plain method.  Each phase's oracle throughput (bytes/s on
+    the slab) is applied to the full step's byte mix to give GB/s."""
+    import oracle
+    slab = np.ascontiguousarray(vol[:slab_z])
+    n = len(bounds) - 1
+    t0 = time.perf_counter()
+    bmin, bmax = oracle.bricks(slab)
+    t1 = time.perf_counter()
+    pd = oracle.pdms(slab, bounds, levels, brick_minmax=(bmin, bmax))
+    t2 = time.perf_counter()
+    upd_bytes = 0
+    Gs = bmin.size
+    for a in alphas[:tfs]:
+        _, m = oracle.tf_update(pd, bounds, a, levels)
+        upd_bytes += (len(oracle.active_list(m, n)) + 1) * Gs
+    t3 = time.perf_counter()
+    for a in alphas[:tfs]:
+        oracle.full_recompute(slab, a, levels)
+    t4 = time.perf_counter()
+    s = slab.dtype.itemsize
+    V = slab.size
+    rate_bricks = (V * s + 2 * Gs * s) / (t1 - t0)
+    rate_parts = (2 * Gs * s + n * Gs) / (t2 - t1)
+    rate_upd = upd_bytes / (t3 - t2)
+    rate_full = tfs * (V * s + Gs) / (t4 - t3)
+    b = step_bytes_fn()
+    est = (b["bricks"] / rate_bricks + b["partitions"] / rate_parts + b["tf_update"] / rate_upd
+           + b["full_recompute"] / rate_full)
+    return {
+        "value": round(b["total"] / est / 1e9, 3),
+        "unit": "GB/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": (f"first {slab_z} of {vol.shape[0]} z-slices ({slab.shape[2]}x{slab.shape[1]}x"
+                   f"{slab_z}), build + {tfs} TFs through update and full recompute, "
+                   f"{t4 - t0:.1f} s; per-phase rates applied to the full step's byte mix"),
+        "tf_update_ms_per_tf_full_volume": round(1e3 * b["tf_update"] / b["tfs"] / rate_upd, 3),
+        "full_recompute_ms_per_tf_full_volume": round(
+            1e3 * b["full_recompute"] / b["tfs"] / rate_full, 3),
+        "build_ms_full_volume": round(1e3 * (b["bricks"] / rate_bricks + b["partitions"] / rate_parts), 1),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tfs", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU layout is a design note, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2407_21552_amd as pdm
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = W.config_info("c3")
+    L, n = cfg["levels"], cfg["n"]
+    log("generating tube-tree 1024x1024x795 u8 ...")
+    vol = W.make_volume("c3")
+    bounds = W.uniform_bounds(L, n)
+    alphas = W.make_tfs("c3", args.tfs)
+    T = len(alphas)
+
+    t_vol = pdm.to_device(vol)
+    v = pdm.Volume(t_vol, L, bounds)
+    desc = v.desc
+    G, V, s = v.G, vol.size, vol.dtype.itemsize
+    d_full = torch.empty_like(v.dist)
+    masks = [pdm.active_set(bounds, a, L) for a in alphas]
+    s_sizes = [len(pdm.mask_to_list(m, n)) for m in masks]
+
+    def step_bytes():
+        b = {
+            "bricks": V * s + 2 * G * s,
+            "partitions": 2 * G * s + n * G,
+            "tf_update": sum((k + 1) * G for k in s_sizes),
+            "full_recompute": T * (V * s + G),
+            "tfs": T,
+        }
+        b["total"] = b["bricks"] + b["partitions"] + b["tf_update"] + b["full_recompute"]
+        return b
+
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def run_step(rec):
+        e = [ev() for _ in range(4)]
+        e[0].record(stream)
+        pdm.build_bricks(desc, t_vol, v.bmin, v.bmax, None, stream)
+        e[1].record(stream)
+        pdm.pom_distance_x(desc, v.bmin, v.bmax, bounds, v.pdms, stream)
+        e[2].record(stream)
+        pdm.distance_yz(desc, v.pdms, n, stream)
+        e[3].record(stream)
+        rec["build"].append(e)
+        for a in alphas:
+            f = [ev() for _ in range(4)]
+            f[0].record(stream)
+            pdm.tf_update(desc, v.pdms, bounds, a, v.dist, stream)
+            f[1].record(stream)
+            pdm.plain_distance_x(desc, t_vol, a, d_full, stream)
+            f[2].record(stream)
+            pdm.distance_yz(desc, d_full, 1, stream)
+            f[3].record(stream)
+            rec["tf"].append(f)
+
+    log(f"warmup {args.warmup} step(s) ...")
+    for _ in range(args.warmup):
+        run_step({"build": [], "tf": []})
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} step(s) of build + {T} TFs ...")
+    rec = {"build": [], "tf": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_step(rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+
+    el = lambda a, b: a.elapsed_time(b)
+    bricks_ms = [el(e[0], e[1]) for e in rec["build"]]
+    pomx_ms = [el(e[1], e[2]) for e in rec["build"]]
+    dyz_n_ms = [el(e[2], e[3]) for e in rec["build"]]
+    upd_ms = [el(f[0], f[1]) for f in rec["tf"]]
+    plx_ms = [el(f[1], f[2]) for f in rec["tf"]]
+    dyz1_ms = [el(f[2], f[3]) for f in rec["tf"]]
+    full_ms = [a + b for a, b in zip(plx_ms, dyz1_ms)]
+    upd_bytes = [(k + 1) * G for k in s_sizes] * args.steps
+    sb = step_bytes()
+
+    # parity spot check on the last TF: D' <= D everywhere (Sec. 3.1)
+    assert bool((v.dist <= d_full).all().item()), "D' > D"
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb} bytes read, {nb} bytes written")
+
+    plain_bytes = V * s + G
+    plain_avg_ms = float(np.mean(plx_ms))
+    plain_gbps = plain_bytes / (plain_avg_ms * 1e-3) / 1e9
+    upd_gbps = sum(upd_bytes) / (sum(upd_ms) * 1e-3) / 1e9
+    traffic = load_traffic()
+
+    def roofline(name, achieved, launches_bytes_note):
+        r = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+             "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+             "traffic": None, "algorithmic": launches_bytes_note}
+        if traffic and name in traffic.get("kernels", {}):
+            r["traffic"] = traffic["kernels"][name]["hbm_bytes_per_launch"]
+        return r
+
+    total_by_kernel = {
+        "k_plain_x": sum(plx_ms), "k_dist_axis(full recompute)": sum(dyz1_ms),
+        "k_combine": sum(upd_ms), "k_bricks": sum(bricks_ms), "k_pom_x": sum(pomx_ms),
+        "k_dist_axis(partitions)": sum(dyz_n_ms)}
+
+    out = {
+        "metric": "TF-update ms & GB/s (partitioned vs full recompute), 1024³ u8; p50/p99 served",
+        "value": round(sb["total"] * args.steps / wall / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded tube-tree volume and trapezoid TFs standing in for kingsnake)",
+        "config": {"workload": "tube-tree 1024x1024x795 u8, bricks 4^3 (256x256x199), "
+                               f"64 uniform partitions, {T} TFs (1-3 ramps); step = build + "
+                               f"{T} x (TF update + full recompute)",
+                   "volume_zyx": list(vol.shape), "partitions": n, "tfs": T, "brick": 4},
+        "tf_update": {"p50_ms": round(pct(upd_ms, 50), 4), "p90_ms": round(pct(upd_ms, 90), 4),
+                      "p99_ms": round(pct(upd_ms, 99), 4), "mean_ms": round(float(np.mean(upd_ms)), 4),
+                      "GBps": round(upd_gbps, 1), "mean_active_partitions": round(float(np.mean(s_sizes)), 2)},
+        "full_recompute": {"p50_ms": round(pct(full_ms, 50), 4), "p90_ms": round(pct(full_ms, 90), 4),
+                           "mean_ms": round(float(np.mean(full_ms)), 4),
+                           "occupancy_x_mean_ms": round(plain_avg_ms, 4),
+                           "distance_yz_mean_ms": round(float(np.mean(dyz1_ms)), 4),
+                           "GBps": round(T * plain_bytes * args.steps / (sum(full_ms) * 1e-3) / 1e9, 1)},
+        "speedup_update_vs_full": {"p50": round(pct(full_ms, 50) / pct(upd_ms, 50), 2),
+                                   "mean": round(float(np.mean(full_ms)) / float(np.mean(upd_ms)), 2)},
+        "build": {"bricks_ms": round(float(np.median(bricks_ms)), 4),
+                  "pom_x_ms": round(float(np.median(pomx_ms)), 4),
+                  "distance_yz_ms": round(float(np.median(dyz_n_ms)), 4),
+                  "total_ms": round(float(np.median(np.add(np.add(bricks_ms, pomx_ms), dyz_n_ms))), 4),
+                  "bricks_GBps": round((V * s + 2 * G * s) / (np.median(bricks_ms) * 1e-3) / 1e9, 1)},
+        "kernel_time_share": {k: round(t / sum(total_by_kernel.values()), 4)
+                              for k, t in total_by_kernel.items()},
+        "roofline": roofline("k_plain_x", plain_gbps,
+                             f"V*s + G = {plain_bytes} B per launch (volume read + x-distance write)"),
+        "roofline_tf_update": roofline("k_combine", upd_gbps,
+                                       "(|S|+1)*G B per launch, summed over the TFs"),
+        "paper_context": PAPER_CONTEXT,
+        "kernel_source_sha256_16": kernel_hash(),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a slab ...")
+        out["cpu_baseline"] = cpu_baseline(vol, bounds, alphas, L, step_bytes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
