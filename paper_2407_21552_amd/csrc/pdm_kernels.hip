@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 // ---------------------------------------------------------------------------
 // k_dist_axis: 1-D max-min pass g(i) = min_j max(|i-j|, f(j)), in place, for
 // lines along y (stride Bx) or z (stride Bx*By).  One lane per line, x
-// fastest so a wave touches 64 consecutive bytes per step.
+// fastest so a wave touches 64 consecutive bytes per step; one wave per
+// work-group.
 //
 // The pass is a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
 // followed by the same pass backwards over F, which yields g exactly (a
@@ -403,80 +404,93 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 // the forward one).  The one-sided pass runs in one sweep: keep v = F(i-1)
 // and W = the latest j attaining it (max(i-1-j, f(j)) <= v).  Then F(i) is
 // min(f(i), X) with X = v if i-W <= v, else v+1; in the second case the new
-// latest witness is W or the latest j in the window with f(j) = v+1, found in
+// latest witness is W or the latest j in the window with f(j) = v+1, held in
 // a per-lane table last[w] = latest position with value w.  Table entries
 // start at 0; a real position 0 is never needed because an accepted entry
 // must exceed W >= 0.
+//
+// Latency: the lookup last[v+1] of step i+1 depends on v = F(i).  Each step
+// therefore reads, one step ahead, the two entries v can lead to besides
+// last[v+1] itself -- last[f(i)+1] (F(i) = f(i)) and last[v+2] (F(i) = v+1)
+// -- and picks one once F(i) is known; an entry equal to the value written
+// in the same step is replaced by that position.  The table load is thus off
+// the dependency chain between steps.
+//
+// Tables: 258 rows (values 0..257, the last two never written) of kPitch
+// entries, lane-major inside a row; the odd dword pitch (17) spreads lanes
+// that look up different values over the LDS banks.
 // ---------------------------------------------------------------------------
-// The per-lane tables of a work-group: 256 rows (one per value w) of TPB
-// entries (one per lane).  The lane's column is XOR-swizzled by w so that
-// lanes looking up different values hit different LDS banks; 64 KiB total.
-template <typename P, int TPB>
-__device__ __forceinline__ int tbl_index(int w, int tid) {
-    constexpr int kScale = 4 / (int)sizeof(P);
-    return w * TPB + (tid ^ ((w * kScale) & (TPB - 1)));
-}
+constexpr int kScanLanes = 64;
+constexpr int kPitch = 68;    // entries per table row (>= kScanLanes)
+constexpr int kRows = 258;
 
-template <typename P, int TPB>
+template <typename P>
 __device__ __forceinline__ void clear_table(P* tbl) {
-    constexpr int kBytes = 256 * TPB * (int)sizeof(P);
+    constexpr int kBytes = ((kRows * kPitch * (int)sizeof(P)) + 15) & ~15;
     uint4* t4 = reinterpret_cast<uint4*>(tbl);
-    for (int i = threadIdx.x; i < kBytes / 16; i += TPB) t4[i] = make_uint4(0, 0, 0, 0);
+    for (int i = threadIdx.x; i < kBytes / 16; i += kScanLanes) t4[i] = make_uint4(0, 0, 0, 0);
 }
 
-template <typename P, int TPB, int CH>
+// One step of the one-sided pass at position i (i >= 1) with input fi.
+// State: v = F(i-1), W its latest witness, t = last[v+1]; ra/rb are the
+// candidates last[f+1], last[v+2] read in the previous step, resolved here by
+// how that step ended (take: F = f; eq: the entry was the one written in
+// that step, at position ip; adv: F = v+1).
+#define PDM_SCAN_STEP(i_, fi_, out_)                                              \
+    {                                                                             \
+        const int i__ = (i_), fi__ = (fi_);                                       \
+        t = take ? ra : (eq ? ip : (adv ? rb : t));                               \
+        ra = (int)tbl[(fi__ + 1) * kPitch + lane];                                \
+        rb = (int)tbl[(v + 2) * kPitch + lane];                                   \
+        adv = (i__ - W) > v;                                                      \
+        const int X__ = v + (adv ? 1 : 0);                                        \
+        take = fi__ <= X__;                                                       \
+        const int Wb__ = adv ? max(W, t) : W;                                     \
+        eq = fi__ == X__ + 1;                                                     \
+        ip = i__;                                                                 \
+        W = take ? i__ : Wb__;                                                    \
+        v = take ? fi__ : X__;                                                    \
+        tbl[fi__ * kPitch + lane] = (P)i__;                                       \
+        out_ = v;                                                                 \
+    }
+
+template <typename P, int CH>
 __device__ __forceinline__ void one_sided(uint8_t* __restrict__ line, int64_t stride, int m,
                                           bool reverse, bool active, P* __restrict__ tbl) {
-    const int tid = threadIdx.x;
-    int v = 0, W = 0;
-    for (int c = 0; c < m; c += CH) {
-        uint32_t f[CH];
+    const int lane = threadIdx.x;
+    const int64_t step = reverse ? -stride : stride;
+    uint8_t* p0 = reverse ? line + (int64_t)(m - 1) * stride : line;
+    // F(0) = f(0); its table entry (position 0) equals the cleared value
+    int v = active ? (int)p0[0] : 0;
+    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
+    bool take = false, adv = false, eq = false;
+    int c = 1;
+    for (; c + CH <= m; c += CH) {
+        int f[CH];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int i = c + k;
-            const int64_t pos = reverse ? (int64_t)(m - 1 - i) : (int64_t)i;
-            f[k] = (active && i < m) ? (uint32_t)line[pos * stride] : 0u;
-        }
+        for (int k = 0; k < CH; ++k) f[k] = active ? (int)p0[(int64_t)(c + k) * step] : 0;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int i = c + k;
-            if (i < m) {
-                const int fi = (int)f[k];
-                if (i == 0) {
-                    v = fi;
-                    W = 0;
-                } else {
-                    const int t = (int)tbl[tbl_index<P, TPB>(min(v + 1, 255), tid)];
-                    const bool adv = (i - W) > v;
-                    const int X = v + (adv ? 1 : 0);
-                    if (fi <= X) {
-                        v = fi;
-                        W = i;
-                    } else if (adv) {
-                        v = X;
-                        W = max(W, t);
-                    }
-                }
-                tbl[tbl_index<P, TPB>(fi, tid)] = (P)i;
-                f[k] = (uint32_t)v;
-            }
-        }
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+        if (active) {
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int i = c + k;
-            const int64_t pos = reverse ? (int64_t)(m - 1 - i) : (int64_t)i;
-            if (active && i < m) line[pos * stride] = (uint8_t)f[k];
+            for (int k = 0; k < CH; ++k) p0[(int64_t)(c + k) * step] = (uint8_t)f[k];
         }
     }
+    for (; c < m; ++c) {
+        const int fi = active ? (int)p0[(int64_t)c * step] : 0;
+        int out;
+        PDM_SCAN_STEP(c, fi, out);
+        if (active) p0[(int64_t)c * step] = (uint8_t)out;
+    }
 }
+#undef PDM_SCAN_STEP
 
-template <typename P, int TPB>
-__global__ void __launch_bounds__(TPB) k_dist_axis(uint8_t* __restrict__ maps, int64_t lines,
-                                                   int Bx, int inner, int64_t plane,
-                                                   int64_t stride, int m, int64_t G) {
-    extern __shared__ __align__(16) unsigned char s_raw[];
-    P* tbl = reinterpret_cast<P*>(s_raw);
-    const int64_t l = (int64_t)blockIdx.x * TPB + threadIdx.x;
+template <typename P>
+__global__ void __launch_bounds__(kScanLanes) k_dist_axis(uint8_t* __restrict__ maps, int64_t lines,
+                                                          int Bx, int inner, int64_t plane,
+                                                          int64_t stride, int m, int64_t G) {
+    __shared__ __align__(16) P tbl[(kRows * kPitch * sizeof(P) + 15) / sizeof(P) & ~(16 / sizeof(P) - 1)];
+    const int64_t l = (int64_t)blockIdx.x * kScanLanes + threadIdx.x;
     const bool active = l < lines;
     uint8_t* line = maps;
     if (active) {
@@ -488,63 +502,87 @@ __global__ void __launch_bounds__(TPB) k_dist_axis(uint8_t* __restrict__ maps, i
         const int64_t g = r / inner;
         line = maps + g * G + a * plane + x;
     }
-    clear_table<P, TPB>(tbl);
+    clear_table<P>(tbl);
     __syncthreads();
-    one_sided<P, TPB, 16>(line, stride, m, false, active, tbl);
+    one_sided<P, 16>(line, stride, m, false, active, tbl);
     __syncthreads();
-    clear_table<P, TPB>(tbl);
+    clear_table<P>(tbl);
     __syncthreads();
-    one_sided<P, TPB, 16>(line, stride, m, true, active, tbl);
+    one_sided<P, 16>(line, stride, m, true, active, tbl);
 }
 
 // ---------------------------------------------------------------------------
-// k_combine: D'[c] = min over the listed partitions of pdms[p*G + c].  Each
-// lane owns 16 consecutive bricks (VEC = 16), 4 (VEC = 4) or 1 (VEC = 1),
-// keeping the running minimum as even/odd byte pairs in packed u16 lanes.
+// k_combine: D'[c] = min over the listed partitions of pdms[p*G + c].
+// VEC = 16: each lane owns two 16-byte vectors, `nthr` vectors apart so that
+// every load instruction of a wave covers 1 KiB of one stream; partitions are
+// taken two at a time, so four 16-byte non-temporal loads are in flight per
+// lane (the PDMs are streamed once per update and do not fit in the caches).
+// The running minimum is kept as even/odd byte pairs in packed u16 lanes.
+// VEC = 4 and VEC = 1 serve sizes or pointers that are not 16-byte aligned.
 // An empty list writes 255.
 // ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 load_nt16(const uint8_t* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ __forceinline__ void min_bytes16(uint32_t (&e)[4], uint32_t (&o)[4], const u32x4 w) {
+    e[0] = pk_min16(e[0], even_bytes(w.x));
+    o[0] = pk_min16(o[0], odd_bytes(w.x));
+    e[1] = pk_min16(e[1], even_bytes(w.y));
+    o[1] = pk_min16(o[1], odd_bytes(w.y));
+    e[2] = pk_min16(e[2], even_bytes(w.z));
+    o[2] = pk_min16(o[2], odd_bytes(w.z));
+    e[3] = pk_min16(e[3], even_bytes(w.w));
+    o[3] = pk_min16(o[3], odd_bytes(w.w));
+}
+
 template <int VEC>
 __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdms, int64_t G,
                                                  ActiveList act, uint8_t* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = act.count;
     if constexpr (VEC == 16) {
-        const int64_t off = t * 16;
-        if (off >= G) return;
-        uint32_t e[4], o[4];
+        const int64_t nvec = G / 16;
+        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+        const int64_t i0 = t, i1 = t + nthr;
+        if (i0 >= nvec) return;
+        const bool two = i1 < nvec;
+        const int64_t o0 = i0 * 16, o1 = two ? i1 * 16 : o0;
+        uint32_t e0[4], d0[4], e1[4], d1[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = o[k] = 0x00FF00FFu;
+        for (int k = 0; k < 4; ++k) e0[k] = d0[k] = e1[k] = d1[k] = 0x00FF00FFu;
         int j = 0;
-        for (; j + 4 <= cnt; j += 4) {
-            uint4 q[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                q[u] = *reinterpret_cast<const uint4*>(pdms + (int64_t)act.p[j + u] * G + off);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    e[k] = pk_min16(e[k], even_bytes(w[k]));
-                    o[k] = pk_min16(o[k], odd_bytes(w[k]));
-                }
-            }
+        for (; j + 2 <= cnt; j += 2) {
+            const uint8_t* pa = pdms + (int64_t)act.p[j] * G;
+            const uint8_t* pb = pdms + (int64_t)act.p[j + 1] * G;
+            const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
+            const u32x4 b0 = load_nt16(pb + o0), b1 = load_nt16(pb + o1);
+            min_bytes16(e0, d0, a0);
+            min_bytes16(e1, d1, a1);
+            min_bytes16(e0, d0, b0);
+            min_bytes16(e1, d1, b1);
         }
-        for (; j < cnt; ++j) {
-            const uint4 q = *reinterpret_cast<const uint4*>(pdms + (int64_t)act.p[j] * G + off);
-            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                e[k] = pk_min16(e[k], even_bytes(w[k]));
-                o[k] = pk_min16(o[k], odd_bytes(w[k]));
-            }
+        if (j < cnt) {
+            const uint8_t* pa = pdms + (int64_t)act.p[j] * G;
+            const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
+            min_bytes16(e0, d0, a0);
+            min_bytes16(e1, d1, a1);
         }
         uint4 r;
-        r.x = e[0] | (o[0] << 8);
-        r.y = e[1] | (o[1] << 8);
-        r.z = e[2] | (o[2] << 8);
-        r.w = e[3] | (o[3] << 8);
-        *reinterpret_cast<uint4*>(out + off) = r;
+        r.x = e0[0] | (d0[0] << 8);
+        r.y = e0[1] | (d0[1] << 8);
+        r.z = e0[2] | (d0[2] << 8);
+        r.w = e0[3] | (d0[3] << 8);
+        *reinterpret_cast<uint4*>(out + o0) = r;
+        if (two) {
+            r.x = e1[0] | (d1[0] << 8);
+            r.y = e1[1] | (d1[1] << 8);
+            r.z = e1[2] | (d1[2] << 8);
+            r.w = e1[3] | (d1[3] << 8);
+            *reinterpret_cast<uint4*>(out + o1) = r;
+        }
     } else if constexpr (VEC == 4) {
         const int64_t off = t * 4;
         if (off >= G) return;
@@ -612,7 +650,7 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
     return hipGetLastError();
 }
 
-template <typename P, int TPB>
+template <typename P>
 static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, int axis,
                               hipStream_t s) {
     const int64_t G = (int64_t)Bx * By * Bz;
@@ -631,9 +669,10 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
         stride = (int64_t)Bx * By;
         m = Bz;
     }
-    const size_t lds = (size_t)256 * TPB * sizeof(P);
-    k_dist_axis<P, TPB><<<blocks_for(lines, TPB), TPB, lds, s>>>(maps, lines, Bx, inner, plane,
-                                                                 stride, m, G);
+    const int64_t blocks = (lines + kScanLanes - 1) / kScanLanes;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    k_dist_axis<P><<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, lines, Bx, inner, plane, stride,
+                                                           m, G);
     return hipGetLastError();
 }
 
@@ -643,9 +682,9 @@ hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, 
         const int m = axis == 1 ? By : Bz;
         if (m == 1) continue;  // a line of one brick is unchanged
         if (m <= 256)
-            e = launch_axis<uint8_t, 256>(maps, count, Bx, By, Bz, axis, s);
+            e = launch_axis<uint8_t>(maps, count, Bx, By, Bz, axis, s);
         else
-            e = launch_axis<uint16_t, 128>(maps, count, Bx, By, Bz, axis, s);
+            e = launch_axis<uint16_t>(maps, count, Bx, By, Bz, axis, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -653,8 +692,8 @@ hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, 
 
 hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
                           int vec, hipStream_t s) {
-    if (vec == 16)
-        k_combine<16><<<blocks_for((G + 15) / 16, 256), 256, 0, s>>>(pdms, G, act, out);
+    if (vec == 16)  // two 16-byte vectors per lane
+        k_combine<16><<<blocks_for((G / 16 + 1) / 2, 256), 256, 0, s>>>(pdms, G, act, out);
     else if (vec == 4)
         k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(pdms, G, act, out);
     else
