@@ -58,6 +58,8 @@ extern "C" {
 #define PDM_MAX_GRID_AXIS 65535 /* bricks per axis */
 #define PDM_MAX_GRID_X 16384    /* bricks along x */
 #define PDM_MAX_PLAIN_LEVELS 16384 /* levels accepted by the plain method */
+#define PDM_MAX_EXACT_LEVELS 16384 /* levels accepted by the EXACT calls */
+#define PDM_MAX_EXACT_GRID_X 256   /* bricks along x accepted by the EXACT build */
 
 typedef enum {
     PDM_OK = 0,
@@ -129,6 +131,29 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
 pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                               uint8_t* d_dist, hipStream_t stream);
 
+/* EXACT occupancy reading (Sec. 3.1, literal wording): a brick is occupied
+ * for an intensity interval when one of its voxels lies in it (for the plain
+ * method: when one of its voxels has non-zero opacity), instead of the RANGE
+ * test on [min, max].  EXACT occupancy is contained in RANGE occupancy, so
+ * EXACT distances are element-wise >= RANGE ones; D' <= D and the equality
+ * case hold within each reading. */
+
+/* PDMs in the EXACT reading, built from the volume directly (no brick
+ * [min, max] needed).  levels <= PDM_MAX_EXACT_LEVELS and
+ * ceil(nx/4) <= PDM_MAX_EXACT_GRID_X, else PDM_E_UNSUPPORTED.  d_pdms: n*G
+ * bytes.  The TF update (pdm_tf_update) is the same for both readings.
+ * Equivalent to pdm_pom_exact_distance_x + pdm_distance_yz(count = n). */
+pdm_status pdm_build_partitions_exact(const pdm_volume* v, const void* d_volume,
+                                      const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                                      hipStream_t stream);
+
+/* Plain method in the EXACT reading: D from the volume, a brick being
+ * occupied when one of its voxels has h_alpha[voxel] != 0.
+ * levels <= PDM_MAX_PLAIN_LEVELS.  Equivalent to pdm_plain_exact_distance_x +
+ * pdm_distance_yz(count = 1). */
+pdm_status pdm_full_recompute_exact(const pdm_volume* v, const void* d_volume,
+                                    const float* h_alpha, uint8_t* d_dist, hipStream_t stream);
+
 /* Phases, exposed so that each kernel can be timed on its own. */
 
 /* First phase of pdm_build_partitions: for every partition, the POM and the
@@ -143,8 +168,17 @@ pdm_status pdm_pom_distance_x(const pdm_volume* v, const void* d_bmin, const voi
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                                 uint8_t* d_dist, hipStream_t stream);
 
-/* Second phase of both: completes `count` stacked grids [count][G] in place
- * from x-only distances to full chessboard distances with 1-D max-min passes
+/* First phase of pdm_build_partitions_exact: EXACT POMs and x distances. */
+pdm_status pdm_pom_exact_distance_x(const pdm_volume* v, const void* d_volume,
+                                    const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                                    hipStream_t stream);
+
+/* First phase of pdm_full_recompute_exact: EXACT occupancy and x distances. */
+pdm_status pdm_plain_exact_distance_x(const pdm_volume* v, const void* d_volume,
+                                      const float* h_alpha, uint8_t* d_dist, hipStream_t stream);
+
+/* Second phase of all of the above: completes `count` stacked grids [count][G]
+ * in place from x-only distances to full chessboard distances with 1-D max-min passes
  * along y and then z, g(i) = min over j of max(|i-j|, f(j)), clamped at 255. */
 pdm_status pdm_distance_yz(const pdm_volume* v, uint8_t* d_maps, int32_t count,
                            hipStream_t stream);

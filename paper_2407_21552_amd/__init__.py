@@ -17,13 +17,19 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, active_set, build_bricks,
-                   build_partitions, distance_yz, full_recompute, grid_of, mask_to_list,
-                   plain_distance_x, pom_distance_x, tf_update, volume_desc)
+                   build_partitions, build_partitions_exact, distance_yz, full_recompute,
+                   full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
+                   plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
+                   volume_desc)
 
-__all__ = ["Volume", "PdmError", "active_set", "build_bricks", "build_partitions", "distance_yz",
-           "full_recompute", "grid_of", "mask_to_list", "plain_distance_x", "pom_distance_x",
-           "tf_update", "volume_desc", "BRICK", "DIST_CAP", "MAX_PARTITIONS", "to_device",
-           "from_device"]
+__all__ = ["Volume", "PdmError", "active_set", "build_bricks", "build_partitions",
+           "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
+           "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
+           "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",
+           "DIST_CAP", "MAX_PARTITIONS", "to_device", "from_device", "RANGE", "EXACT"]
+
+RANGE = "range"  # occupancy from the brick's [min, max] interval
+EXACT = "exact"  # occupancy from the brick's voxels (Sec. 3.1 wording)
 
 
 def to_device(arr: np.ndarray, device="cuda"):
@@ -47,10 +53,15 @@ class Volume:
     """One volume resident on the GPU with its bricks, PDMs and output map.
 
     t_volume: contiguous (nz, ny, nx) tensor of uint8, or int16 holding the
-    bits of uint16 intensities (dtype given by `voxel_dtype`)."""
+    bits of uint16 intensities (dtype given by `voxel_dtype`).  `mode` selects
+    the occupancy reading of both the PDMs and the plain method: RANGE (brick
+    [min, max]) or EXACT (brick voxels)."""
 
-    def __init__(self, t_volume, levels: int, bounds, voxel_dtype=None):
+    def __init__(self, t_volume, levels: int, bounds, voxel_dtype=None, mode: str = RANGE):
         import torch
+        if mode not in (RANGE, EXACT):
+            raise ValueError(f"mode must be {RANGE!r} or {EXACT!r}")
+        self.mode = mode
         if voxel_dtype is None:
             voxel_dtype = np.uint8 if t_volume.dtype == torch.uint8 else np.uint16
         self.voxel_dtype = np.dtype(voxel_dtype)
@@ -75,7 +86,10 @@ class Volume:
     def build(self, stream=None) -> None:
         """One-time initialisation: brick [min,max], then every PDM."""
         build_bricks(self.desc, self.volume, self.bmin, self.bmax, self.range_err, stream)
-        build_partitions(self.desc, self.bmin, self.bmax, self.bounds, self.pdms, stream)
+        if self.mode == EXACT:
+            build_partitions_exact(self.desc, self.volume, self.bounds, self.pdms, stream)
+        else:
+            build_partitions(self.desc, self.bmin, self.bmax, self.bounds, self.pdms, stream)
 
     def check_range(self) -> None:
         """Synchronises; raises PdmError if some voxel was >= levels."""
@@ -89,4 +103,5 @@ class Volume:
 
     def full_recompute(self, alpha, out=None, stream=None) -> None:
         """Plain method: D from the raw volume."""
-        full_recompute(self.desc, self.volume, alpha, self.dist if out is None else out, stream)
+        fn = full_recompute_exact if self.mode == EXACT else full_recompute
+        fn(self.desc, self.volume, alpha, self.dist if out is None else out, stream)

@@ -63,9 +63,15 @@ def lib() -> ctypes.CDLL:
         L.pdm_pom_distance_x.argtypes = [V, P, P, P, i32, P, P]
         L.pdm_plain_distance_x.argtypes = [V, P, P, P, P]
         L.pdm_distance_yz.argtypes = [V, P, i32, P]
+        L.pdm_build_partitions_exact.argtypes = [V, P, P, i32, P, P]
+        L.pdm_pom_exact_distance_x.argtypes = [V, P, P, i32, P, P]
+        L.pdm_full_recompute_exact.argtypes = [V, P, P, P, P]
+        L.pdm_plain_exact_distance_x.argtypes = [V, P, P, P, P]
         for name in ("pdm_grid_of", "pdm_active_set", "pdm_build_bricks", "pdm_build_partitions",
                      "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
-                     "pdm_plain_distance_x", "pdm_distance_yz"):
+                     "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
+                     "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
+                     "pdm_plain_exact_distance_x"):
             getattr(L, name).restype = st
         L.pdm_status_string.argtypes = [st]
         L.pdm_status_string.restype = ctypes.c_char_p
@@ -236,3 +242,44 @@ def plain_distance_x(desc, volume, alpha, dist, stream=None) -> None:
                                       _dev_ptr(volume, _vox_bytes(desc), "volume"), _np_ptr(a),
                                       _dev_ptr(dist, G, "dist"), _stream(stream)),
            "pdm_plain_distance_x")
+
+
+# ------------------------------------------------------- EXACT occupancy
+def build_partitions_exact(desc, volume, bounds, pdms, stream=None) -> None:
+    """PDMs with EXACT POMs (a voxel of the brick in the partition), from the volume."""
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    _check(lib().pdm_build_partitions_exact(ctypes.byref(desc),
+                                            _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                            _np_ptr(b), n, _dev_ptr(pdms, n * G, "pdms"),
+                                            _stream(stream)), "pdm_build_partitions_exact")
+
+
+def pom_exact_distance_x(desc, volume, bounds, pdms, stream=None) -> None:
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    _check(lib().pdm_pom_exact_distance_x(ctypes.byref(desc),
+                                          _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                          _np_ptr(b), n, _dev_ptr(pdms, n * G, "pdms"),
+                                          _stream(stream)), "pdm_pom_exact_distance_x")
+
+
+def full_recompute_exact(desc, volume, alpha, dist, stream=None) -> None:
+    """Plain method with EXACT occupancy (a voxel of the brick has alpha != 0)."""
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_full_recompute_exact(ctypes.byref(desc),
+                                          _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                          _np_ptr(a), _dev_ptr(dist, G, "dist"), _stream(stream)),
+           "pdm_full_recompute_exact")
+
+
+def plain_exact_distance_x(desc, volume, alpha, dist, stream=None) -> None:
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_plain_exact_distance_x(ctypes.byref(desc),
+                                            _dev_ptr(volume, _vox_bytes(desc), "volume"),
+                                            _np_ptr(a), _dev_ptr(dist, G, "dist"),
+                                            _stream(stream)), "pdm_plain_exact_distance_x")

@@ -6,7 +6,7 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "../../include/pdm.h"
+#include "pdm.h"
 #include "pdm_launch.h"
 
 namespace {
@@ -58,6 +58,35 @@ void active_mask(const int32_t* b, int32_t n, const float* alpha, uint64_t mask[
 }
 
 pdm_status from_hip(hipError_t e) { return e == hipSuccess ? PDM_OK : PDM_E_DEVICE; }
+
+// Validation and kernel arguments shared by both readings of the plain
+// method: the non-zero opacity bitmap and the volume geometry.
+pdm_status plain_args(const pdm_volume* v, const void* d_volume, const float* h_alpha,
+                      uint8_t* d_dist, pdm::PlainArgs* a, AlphaBits* bits) {
+    pdm_grid g;
+    const pdm_status st = check_volume(v, &g);
+    if (st != PDM_OK) return st;
+    if (d_volume == nullptr || h_alpha == nullptr || d_dist == nullptr) return PDM_E_INVAL;
+    if (v->levels > PDM_MAX_PLAIN_LEVELS) return PDM_E_UNSUPPORTED;
+    memset(bits, 0, sizeof(*bits));
+    for (int32_t i = 0; i < v->levels; ++i)
+        if (h_alpha[i] != 0.0f) bits->w[i >> 5] |= 1u << (i & 31);
+    a->vol = d_volume;
+    a->dist = d_dist;
+    a->nx = v->nx;
+    a->ny = v->ny;
+    a->nz = v->nz;
+    a->Bx = g.bx;
+    a->By = g.by;
+    a->Bz = g.bz;
+    a->bytes = v->dtype;
+    a->nwords = (v->levels + 31) / 32;
+    a->levels = v->levels;
+    a->vec_ok = ((int64_t)v->nx * v->dtype) % 16 == 0 && aligned(d_volume, 16);
+    a->store_vec = g.bx % 4 == 0 && aligned(d_dist, 4);
+    return PDM_OK;
+}
+
 
 }  // namespace
 
@@ -175,18 +204,37 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
 
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                                 uint8_t* d_dist, hipStream_t stream) {
-    pdm_grid g;
-    const pdm_status st = check_volume(v, &g);
-    if (st != PDM_OK) return st;
-    if (d_volume == nullptr || h_alpha == nullptr || d_dist == nullptr) return PDM_E_INVAL;
-    if (v->levels > PDM_MAX_PLAIN_LEVELS) return PDM_E_UNSUPPORTED;
-    AlphaBits bits;
-    memset(&bits, 0, sizeof(bits));
-    for (int32_t i = 0; i < v->levels; ++i)
-        if (h_alpha[i] != 0.0f) bits.w[i >> 5] |= 1u << (i & 31);
     pdm::PlainArgs a;
+    AlphaBits bits;
+    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits);
+    if (st != PDM_OK) return st;
+    return from_hip(pdm::launch_plain_x(a, bits, stream));
+}
+
+pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
+                              uint8_t* d_dist, hipStream_t stream) {
+    pdm_status st = pdm_plain_distance_x(v, d_volume, h_alpha, d_dist, stream);
+    if (st != PDM_OK) return st;
+    return pdm_distance_yz(v, d_dist, 1, stream);
+}
+
+pdm_status pdm_pom_exact_distance_x(const pdm_volume* v, const void* d_volume,
+                                    const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                                    hipStream_t stream) {
+    pdm_grid g;
+    pdm_status st = check_volume(v, &g);
+    if (st != PDM_OK) return st;
+    if (d_volume == nullptr || d_pdms == nullptr) return PDM_E_INVAL;
+    st = check_bounds(h_bounds, n, v->levels);
+    if (st != PDM_OK) return st;
+    if (v->levels > PDM_MAX_EXACT_LEVELS || g.bx > PDM_MAX_EXACT_GRID_X) return PDM_E_UNSUPPORTED;
+    Bounds b;
+    memset(&b, 0, sizeof(b));
+    for (int32_t p = 0; p <= n; ++p) b.b[p] = h_bounds[p];
+    pdm::PomExactArgs a;
     a.vol = d_volume;
-    a.dist = d_dist;
+    a.pdms = d_pdms;
+    a.G = g.count;
     a.nx = v->nx;
     a.ny = v->ny;
     a.nz = v->nz;
@@ -194,16 +242,33 @@ pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const
     a.By = g.by;
     a.Bz = g.bz;
     a.bytes = v->dtype;
-    a.nwords = (v->levels + 31) / 32;
+    a.n = n;
     a.levels = v->levels;
     a.vec_ok = ((int64_t)v->nx * v->dtype) % 16 == 0 && aligned(d_volume, 16);
-    a.store_vec = g.bx % 4 == 0 && aligned(d_dist, 4);
-    return from_hip(pdm::launch_plain_x(a, bits, stream));
+    a.store_vec = g.bx % 4 == 0 && aligned(d_pdms, 4);
+    return from_hip(pdm::launch_pom_exact_x(a, b, stream));
 }
 
-pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
-                              uint8_t* d_dist, hipStream_t stream) {
-    pdm_status st = pdm_plain_distance_x(v, d_volume, h_alpha, d_dist, stream);
+pdm_status pdm_build_partitions_exact(const pdm_volume* v, const void* d_volume,
+                                      const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
+                                      hipStream_t stream) {
+    pdm_status st = pdm_pom_exact_distance_x(v, d_volume, h_bounds, n, d_pdms, stream);
+    if (st != PDM_OK) return st;
+    return pdm_distance_yz(v, d_pdms, n, stream);
+}
+
+pdm_status pdm_plain_exact_distance_x(const pdm_volume* v, const void* d_volume,
+                                      const float* h_alpha, uint8_t* d_dist, hipStream_t stream) {
+    pdm::PlainArgs a;
+    AlphaBits bits;
+    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits);
+    if (st != PDM_OK) return st;
+    return from_hip(pdm::launch_plain_exact_x(a, bits, stream));
+}
+
+pdm_status pdm_full_recompute_exact(const pdm_volume* v, const void* d_volume,
+                                    const float* h_alpha, uint8_t* d_dist, hipStream_t stream) {
+    pdm_status st = pdm_plain_exact_distance_x(v, d_volume, h_alpha, d_dist, stream);
     if (st != PDM_OK) return st;
     return pdm_distance_yz(v, d_dist, 1, stream);
 }

@@ -18,6 +18,9 @@
 //   k_dist_axis     x distances -> full chessboard distances: 1-D max-min pass
 //                   along y or z, one lane per line, linear-time scan.
 //   k_combine       masked min over the active PDM streams, 16 bytes per lane.
+//   k_pom_exact_x   EXACT reading: per-brick partition masks from the voxels,
+//                   then the x distances of every partition.
+//   k_plain_exact_x EXACT reading of the plain method's occupancy.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -393,10 +396,157 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 }
 
 // ---------------------------------------------------------------------------
+// EXACT occupancy (a brick is occupied when one of its voxels qualifies, the
+// literal POM wording of Sec. 3.1), for the PDM build and the plain method.
+// ---------------------------------------------------------------------------
+
+// Calls f(k, value) for every voxel of the 4 bricks x = 4q..4q+3 of brick row
+// (bz, by) that lies inside the volume (k = brick within the quad).
+template <typename T, typename F>
+__device__ __forceinline__ void quad_voxels(const T* __restrict__ vol, int nx, int ny, int nz, int q,
+                                            int by, int bz, bool vec_ok, F f) {
+    const int x0 = 16 * q;
+    const int z0 = 4 * bz, y0 = 4 * by;
+    const int zn = min(4, nz - z0), yn = min(4, ny - y0);
+    if (vec_ok && x0 + 16 <= nx) {
+        for (int zz = 0; zz < zn; ++zz) {
+#pragma unroll
+            for (int yy = 0; yy < 4; ++yy) {
+                if (yy < yn) {
+                    const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+                    if constexpr (sizeof(T) == 1) {
+                        const uint4 w = *reinterpret_cast<const uint4*>(vol + off);
+                        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) f(k, (ws[k] >> (8 * b)) & 0xFFu);
+                    } else {
+                        const uint4* p = reinterpret_cast<const uint4*>(vol + off);
+                        const uint4 a = p[0], c = p[1];
+                        const uint32_t ws[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            f(k, lo16(ws[2 * k]));
+                            f(k, hi16(ws[2 * k]));
+                            f(k, lo16(ws[2 * k + 1]));
+                            f(k, hi16(ws[2 * k + 1]));
+                        }
+                    }
+                }
+            }
+        }
+    } else {
+        const int xn = min(16, nx - x0);
+        for (int zz = 0; zz < zn; ++zz)
+            for (int yy = 0; yy < yn; ++yy) {
+                const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int xx = 0; xx < 4; ++xx)
+                        if (4 * k + xx < xn) f(k, (uint32_t)vol[off + 4 * k + xx]);
+            }
+    }
+}
+
+// k_pom_exact_x: one wave per brick row (Bx <= 256).  Each lane marks, for
+// its 4 bricks, which partitions hold one of their voxels (NW = ceil(n/32)
+// mask words per brick, from an LDS table intensity -> partition), then the
+// wave computes every partition's x distances from those masks.  Reads the
+// volume once and writes n*G bytes.
+template <typename T, int NW>
+__global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, int nx, int ny,
+                                                     int nz, int Bx, int By, int64_t rows,
+                                                     Bounds bounds, int n, int levels,
+                                                     uint8_t* __restrict__ pdms, int64_t G,
+                                                     int vec_ok, int store_vec) {
+    __shared__ uint8_t s_part[PDM_EXACT_MAX_LEVELS];
+    // partition p paints its intensities [bounds[p], bounds[p+1])
+    for (int p = threadIdx.x; p < n; p += blockDim.x)
+        for (int v = bounds.b[p]; v < bounds.b[p + 1]; ++v) s_part[v] = (uint8_t)p;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (row >= rows) return;  // wave-uniform, after the barrier
+    const int by = (int)(row % By), bz = (int)(row / By);
+    const int64_t rbase = row * Bx;
+    uint32_t mk[4][NW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) mk[k][w] = 0u;
+    const uint32_t top = (uint32_t)levels - 1u;  // voxels >= levels break the precondition
+    if (4 * lane < Bx) {
+        quad_voxels<T>(vol, nx, ny, nz, lane, by, bz, vec_ok != 0, [&](int k, uint32_t val) {
+            const uint32_t pid = s_part[umin(val, top)];
+            const uint32_t bit = 1u << (pid & 31u);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mk[k][w] |= ((pid >> 5) == (uint32_t)w) ? bit : 0u;
+        });
+    }
+    const int nb = max(0, min(4, Bx - 4 * lane));
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int pend = min(32, n - 32 * w);
+        for (int b = 0; b < pend; ++b) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o |= ((mk[k][w] >> b) & 1u) << k;
+            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
+            if (nb > 0)
+                store_quad(pdms + (int64_t)(32 * w + b) * G, rbase + 4 * lane, nb, packed, store_vec);
+        }
+    }
+}
+
+// k_plain_exact_x: the plain method's occupancy in the EXACT reading (some
+// voxel of the brick has alpha != 0, looked up in the LDS bitmap) and its x
+// distances; long rows in 256-brick segments as in k_plain_x.
+template <typename T>
+__global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol, int nx, int ny,
+                                                       int nz, int Bx, int By, int64_t rows,
+                                                       AlphaBits bits, int nwords, int levels,
+                                                       uint8_t* __restrict__ dist, int vec_ok,
+                                                       int store_vec) {
+    __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
+    __shared__ uint8_t s_nib[4][kMaxSegs][kWave];
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+    if (row >= rows) return;  // wave-uniform, after the barrier
+    const int by = (int)(row % By), bz = (int)(row / By);
+    const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
+    const int64_t rbase = row * Bx;
+    const uint32_t top = (uint32_t)levels - 1u;
+    for (int s = 0; s < nseg; ++s) {
+        const int q = s * kWave + lane;
+        uint32_t o = 0;
+        if (4 * q < Bx) {
+            quad_voxels<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0, [&](int k, uint32_t val) {
+                const uint32_t v = umin(val, top);
+                o |= ((s_words[v >> 5] >> (v & 31u)) & 1u) << k;
+            });
+        }
+        s_nib[wv][s][lane] = (uint8_t)o;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int s = 0; s < nseg; ++s) {
+        const int xs = s * kSegBricks;
+        const uint32_t cur = s_nib[wv][s][lane];
+        const int prev_last = s > 0 ? seg_last(s_nib[wv][s - 1][lane], xs - kSegBricks) : -kNone;
+        const int next_first = s + 1 < nseg ? seg_first(s_nib[wv][s + 1][lane], xs + kSegBricks) : kNone;
+        const uint32_t packed = x_distances(cur, lane, xs, prev_last, next_first);
+        const int nb = max(0, min(4, Bx - xs - 4 * lane));
+        if (nb > 0) store_quad(dist, rbase + xs + 4 * lane, nb, packed, store_vec);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_dist_axis: 1-D max-min pass g(i) = min_j max(|i-j|, f(j)), in place, for
-// lines along y (stride Bx) or z (stride Bx*By).  One lane per line, x
-// fastest so a wave touches 64 consecutive bytes per step; one wave per
-// work-group.
+// lines along y (stride Bx) or z (stride Bx*By), one lane per line.
 //
 // The pass is a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
 // followed by the same pass backwards over F, which yields g exactly (a
@@ -421,8 +571,13 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 // that look up different values over the LDS banks.
 // ---------------------------------------------------------------------------
 constexpr int kScanLanes = 64;
-constexpr int kPitch = 68;    // entries per table row (>= kScanLanes)
+constexpr int kPitch = 68;      // entries per table row (>= kScanLanes)
 constexpr int kRows = 258;
+constexpr int kMaxLine = 256;   // longest line staged in LDS
+// Passes over at most this many lines use the LDS-staged kernel: they cannot
+// fill the chip's 1024 SIMDs with more than a few waves each, so per-wave
+// latency matters more than occupancy.
+constexpr int64_t kStagedMaxLines = 4 * 1024 * kScanLanes;
 
 template <typename P>
 __device__ __forceinline__ void clear_table(P* tbl) {
@@ -433,82 +588,168 @@ __device__ __forceinline__ void clear_table(P* tbl) {
 
 // One step of the one-sided pass at position i (i >= 1) with input fi.
 // State: v = F(i-1), W its latest witness, t = last[v+1]; ra/rb are the
-// candidates last[f+1], last[v+2] read in the previous step, resolved here by
-// how that step ended (take: F = f; eq: the entry was the one written in
-// that step, at position ip; adv: F = v+1).
+// candidates last[f+1], last[v+2] read in the previous step and resolved in
+// this one by how that step ended (take: F = f; eq: the entry was the one
+// written in that step, at position ip; adv: F = v+1).  The empty asm pins
+// the point where those loads must have returned to after this step's own
+// loads are issued, so the table latency overlaps a step of arithmetic.
 #define PDM_SCAN_STEP(i_, fi_, out_)                                              \
     {                                                                             \
         const int i__ = (i_), fi__ = (fi_);                                       \
+        const int ran__ = (int)tbl[__umul24((unsigned)fi__ + 1u, kPitch) + lane];                   \
+        const int rbn__ = (int)tbl[__umul24((unsigned)v + 2u, kPitch) + lane];                      \
+        const bool advn__ = (i__ - W) > v;                                        \
+        const int X__ = v + (advn__ ? 1 : 0);                                     \
+        const bool taken__ = fi__ <= X__;                                         \
+        const bool eqn__ = fi__ == X__ + 1;                                       \
+        __asm__ volatile("" : "+v"(ra), "+v"(rb));                                \
         t = take ? ra : (eq ? ip : (adv ? rb : t));                               \
-        ra = (int)tbl[(fi__ + 1) * kPitch + lane];                                \
-        rb = (int)tbl[(v + 2) * kPitch + lane];                                   \
-        adv = (i__ - W) > v;                                                      \
-        const int X__ = v + (adv ? 1 : 0);                                        \
-        take = fi__ <= X__;                                                       \
-        const int Wb__ = adv ? max(W, t) : W;                                     \
-        eq = fi__ == X__ + 1;                                                     \
+        const int Wb__ = advn__ ? max(W, t) : W;                                  \
+        W = taken__ ? i__ : Wb__;                                                 \
+        v = taken__ ? fi__ : X__;                                                 \
+        take = taken__;                                                           \
+        eq = eqn__;                                                               \
+        adv = advn__;                                                             \
         ip = i__;                                                                 \
-        W = take ? i__ : Wb__;                                                    \
-        v = take ? fi__ : X__;                                                    \
-        tbl[fi__ * kPitch + lane] = (P)i__;                                       \
+        ra = ran__;                                                               \
+        rb = rbn__;                                                               \
+        tbl[__umul24((unsigned)fi__, kPitch) + lane] = (P)i__;                                       \
         out_ = v;                                                                 \
     }
 
+// The one-sided pass over one line held in an LDS column: col[k * cs] for
+// k = 0..m-1 in the pass's direction (cs may be negative), overwritten in
+// place with the result.  Values are read CH at a time into registers before
+// their steps run.
 template <typename P, int CH>
-__device__ __forceinline__ void one_sided(uint8_t* __restrict__ line, int64_t stride, int m,
-                                          bool reverse, bool active, P* __restrict__ tbl) {
+__device__ __forceinline__ void one_sided_lds(uint8_t* col, int cs, int m, P* __restrict__ tbl) {
     const int lane = threadIdx.x;
-    const int64_t step = reverse ? -stride : stride;
-    uint8_t* p0 = reverse ? line + (int64_t)(m - 1) * stride : line;
     // F(0) = f(0); its table entry (position 0) equals the cleared value
-    int v = active ? (int)p0[0] : 0;
+    int v = col[0];
     int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
     bool take = false, adv = false, eq = false;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) f[k] = active ? (int)p0[(int64_t)(c + k) * step] : 0;
+        for (int k = 0; k < CH; ++k) f[k] = col[(c + k) * cs];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) col[(c + k) * cs] = (uint8_t)f[k];
+    }
+    for (; c < m; ++c) {
+        int out;
+        PDM_SCAN_STEP(c, (int)col[c * cs], out);
+        col[c * cs] = (uint8_t)out;
+    }
+}
+
+// The same pass over a line in global memory, p[k * step] (lines longer
+// than the LDS tile); `active` false lanes only keep the wave in step.
+template <typename P, int CH>
+__device__ __forceinline__ void one_sided_global(uint8_t* p, int64_t step, int m, bool active,
+                                                 P* __restrict__ tbl) {
+    const int lane = threadIdx.x;
+    int v = active ? (int)p[0] : 0;
+    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
+    bool take = false, adv = false, eq = false;
+    int c = 1;
+    for (; c + CH <= m; c += CH) {
+        int f[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) f[k] = active ? (int)p[(int64_t)(c + k) * step] : 0;
 #pragma unroll
         for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
         if (active) {
 #pragma unroll
-            for (int k = 0; k < CH; ++k) p0[(int64_t)(c + k) * step] = (uint8_t)f[k];
+            for (int k = 0; k < CH; ++k) p[(int64_t)(c + k) * step] = (uint8_t)f[k];
         }
     }
     for (; c < m; ++c) {
-        const int fi = active ? (int)p0[(int64_t)c * step] : 0;
+        const int fi = active ? (int)p[(int64_t)c * step] : 0;
         int out;
         PDM_SCAN_STEP(c, fi, out);
-        if (active) p0[(int64_t)c * step] = (uint8_t)out;
+        if (active) p[(int64_t)c * step] = (uint8_t)out;
     }
 }
 #undef PDM_SCAN_STEP
 
-template <typename P>
+// Line l of a pass: x fastest, then the other in-grid axis (`inner` values
+// with step `plane`), then the grid index.
+__device__ __forceinline__ int64_t line_offset(int64_t l, int Bx, int inner, int64_t plane,
+                                               int64_t G) {
+    const int64_t r = l / Bx;
+    return (r / inner) * G + (r % inner) * plane + l % Bx;
+}
+
+// Lines of at most kMaxLine bricks.  One wave per work-group handles 64
+// lines, staged into LDS ([pos][lane], 64 bytes per position) so that no
+// step waits on global memory.  With `wide` set (the 64 lines are
+// x0..x0+63 of one row and rows are 16-byte aligned) the staging moves 16
+// bytes per lane per instruction, 16 positions per wave instruction;
+// otherwise one byte per lane.
 __global__ void __launch_bounds__(kScanLanes) k_dist_axis(uint8_t* __restrict__ maps, int64_t lines,
                                                           int Bx, int inner, int64_t plane,
-                                                          int64_t stride, int m, int64_t G) {
-    __shared__ __align__(16) P tbl[(kRows * kPitch * sizeof(P) + 15) / sizeof(P) & ~(16 / sizeof(P) - 1)];
+                                                          int64_t stride, int m, int64_t G,
+                                                          int wide) {
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    __shared__ __align__(16) uint8_t tile[kMaxLine * kScanLanes];
+    const int lane = threadIdx.x;
+    const int64_t l0 = (int64_t)blockIdx.x * kScanLanes;
+    const int64_t l = l0 + lane;
+    const bool active = l < lines;
+    const int q = lane & 3;  // 16-byte quarter of a 64-byte row
+    if (wide) {
+        const uint8_t* base = maps + line_offset(l0, Bx, inner, plane, G);
+        for (int r = lane >> 2; r < m; r += 16)
+            *reinterpret_cast<uint4*>(&tile[r * kScanLanes + 16 * q]) =
+                *reinterpret_cast<const uint4*>(base + (int64_t)r * stride + 16 * q);
+    } else {
+        const uint8_t* line = maps + (active ? line_offset(l, Bx, inner, plane, G) : 0);
+        for (int r = 0; r < m; ++r)
+            tile[r * kScanLanes + lane] = active ? line[(int64_t)r * stride] : (uint8_t)0;
+    }
+    clear_table<uint8_t>(tbl);
+    __syncthreads();
+    one_sided_lds<uint8_t, 16>(&tile[lane], kScanLanes, m, tbl);
+    __syncthreads();
+    clear_table<uint8_t>(tbl);
+    __syncthreads();
+    one_sided_lds<uint8_t, 16>(&tile[(m - 1) * kScanLanes + lane], -kScanLanes, m, tbl);
+    __syncthreads();
+    if (wide) {
+        uint8_t* base = maps + line_offset(l0, Bx, inner, plane, G);
+        for (int r = lane >> 2; r < m; r += 16)
+            *reinterpret_cast<uint4*>(base + (int64_t)r * stride + 16 * q) =
+                *reinterpret_cast<const uint4*>(&tile[r * kScanLanes + 16 * q]);
+    } else if (active) {
+        uint8_t* line = maps + line_offset(l, Bx, inner, plane, G);
+        for (int r = 0; r < m; ++r) line[(int64_t)r * stride] = tile[r * kScanLanes + lane];
+    }
+}
+
+// The scan on global memory directly, one lane per line, 64 lanes per
+// work-group and only the table in LDS (17.5 KB with 8-bit entries), so up to
+// nine waves share a compute unit: the choice when the passes cover many
+// lines (all partitions at once) and occupancy hides the memory latency.
+// P = uint16_t serves lines longer than 256 bricks (positions beyond 255).
+template <typename P>
+__global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict__ maps,
+                                                            int64_t lines, int Bx, int inner,
+                                                            int64_t plane, int64_t stride, int m,
+                                                            int64_t G) {
+    __shared__ __align__(16) P tbl[((kRows * kPitch * sizeof(P) + 15) & ~15) / sizeof(P)];
     const int64_t l = (int64_t)blockIdx.x * kScanLanes + threadIdx.x;
     const bool active = l < lines;
-    uint8_t* line = maps;
-    if (active) {
-        // line l: x fastest, then the other in-grid axis (`inner` values with
-        // step `plane`), then the grid index
-        const int64_t x = l % Bx;
-        const int64_t r = l / Bx;
-        const int64_t a = r % inner;
-        const int64_t g = r / inner;
-        line = maps + g * G + a * plane + x;
-    }
+    uint8_t* line = maps + (active ? line_offset(l, Bx, inner, plane, G) : 0);
     clear_table<P>(tbl);
     __syncthreads();
-    one_sided<P, 16>(line, stride, m, false, active, tbl);
+    one_sided_global<P, 16>(line, stride, m, active, tbl);
     __syncthreads();
     clear_table<P>(tbl);
     __syncthreads();
-    one_sided<P, 16>(line, stride, m, true, active, tbl);
+    one_sided_global<P, 16>(line + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
 }
 
 // ---------------------------------------------------------------------------
@@ -650,41 +891,96 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
     return hipGetLastError();
 }
 
-template <typename P>
-static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, int axis,
-                              hipStream_t s) {
-    const int64_t G = (int64_t)Bx * By * Bz;
+template <typename T>
+static hipError_t launch_pom_exact_t(const PomExactArgs& a, const Bounds& b, hipStream_t s) {
+    const int64_t rows = (int64_t)a.By * a.Bz;
+    const unsigned nb = blocks_for(rows, 4);
+    const int nw = (a.n + 31) / 32;
+#define PDM_LAUNCH_EXACT(NW)                                                                   \
+    k_pom_exact_x<T, NW><<<nb, 256, 0, s>>>((const T*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By, rows, \
+                                            b, a.n, a.levels, a.pdms, a.G, a.vec_ok,            \
+                                            a.store_vec)
+    if (nw == 1)
+        PDM_LAUNCH_EXACT(1);
+    else if (nw == 2)
+        PDM_LAUNCH_EXACT(2);
+    else if (nw <= 4)
+        PDM_LAUNCH_EXACT(4);
+    else
+        PDM_LAUNCH_EXACT(8);
+#undef PDM_LAUNCH_EXACT
+    return hipGetLastError();
+}
+
+hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s) {
+    return a.bytes == 1 ? launch_pom_exact_t<uint8_t>(a, b, s) : launch_pom_exact_t<uint16_t>(a, b, s);
+}
+
+hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s) {
+    const int64_t rows = (int64_t)a.By * a.Bz;
+    const unsigned nb = blocks_for(rows, 4);
+    if (a.bytes == 1)
+        k_plain_exact_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                                    a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                                    a.vec_ok, a.store_vec);
+    else
+        k_plain_exact_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                                     a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                                     a.vec_ok, a.store_vec);
+    return hipGetLastError();
+}
+
+// Line geometry of a pass along y (axis 1) or z (axis 2) over `count` grids.
+struct AxisLines {
     int64_t lines, plane, stride;
     int inner, m;
+};
+
+static AxisLines axis_lines(int count, int Bx, int By, int Bz, int axis) {
+    AxisLines a;
     if (axis == 1) {  // along y: lines (g, z, x)
-        lines = (int64_t)count * Bx * Bz;
-        inner = Bz;
-        plane = (int64_t)Bx * By;
-        stride = Bx;
-        m = By;
+        a.lines = (int64_t)count * Bx * Bz;
+        a.inner = Bz;
+        a.plane = (int64_t)Bx * By;
+        a.stride = Bx;
+        a.m = By;
     } else {  // along z: lines (g, y, x)
-        lines = (int64_t)count * Bx * By;
-        inner = By;
-        plane = Bx;
-        stride = (int64_t)Bx * By;
-        m = Bz;
+        a.lines = (int64_t)count * Bx * By;
+        a.inner = By;
+        a.plane = Bx;
+        a.stride = (int64_t)Bx * By;
+        a.m = Bz;
     }
-    const int64_t blocks = (lines + kScanLanes - 1) / kScanLanes;
+    return a;
+}
+
+static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, int axis,
+                              hipStream_t s) {
+    const AxisLines a = axis_lines(count, Bx, By, Bz, axis);
+    const int64_t G = (int64_t)Bx * By * Bz;
+    const int64_t blocks = (a.lines + kScanLanes - 1) / kScanLanes;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    k_dist_axis<P><<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, lines, Bx, inner, plane, stride,
-                                                           m, G);
+    if (a.m > kMaxLine) {
+        k_dist_global<uint16_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
+            maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+    } else if (a.lines > kStagedMaxLines) {
+        k_dist_global<uint8_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
+            maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+    } else {
+        // 16-byte staging: groups of 64 lines never straddle a row, rows and
+        // the map base are 16-byte aligned
+        const int wide = Bx % kScanLanes == 0 && a.stride % 16 == 0 && ((uintptr_t)maps & 15) == 0;
+        k_dist_axis<<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, a.plane,
+                                                            a.stride, a.m, G, wide);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s) {
-    hipError_t e;
     for (int axis = 1; axis <= 2; ++axis) {
         const int m = axis == 1 ? By : Bz;
         if (m == 1) continue;  // a line of one brick is unchanged
-        if (m <= 256)
-            e = launch_axis<uint8_t>(maps, count, Bx, By, Bz, axis, s);
-        else
-            e = launch_axis<uint16_t>(maps, count, Bx, By, Bz, axis, s);
+        const hipError_t e = launch_axis(maps, count, Bx, By, Bz, axis, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

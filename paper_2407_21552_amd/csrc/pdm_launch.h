@@ -6,6 +6,8 @@
 
 #define PDM_PLAIN_MAX_SEGS 64    // x segments of 256 bricks: Bx <= 16384
 #define PDM_ALPHA_WORDS 512      // non-zero opacity bitmap: levels <= 16384
+#define PDM_EXACT_MAX_LEVELS 16384  // intensity -> partition table of the EXACT build
+
 
 namespace pdm {
 
@@ -51,9 +53,19 @@ struct PlainArgs {
     int vec_ok, store_vec;
 };
 
+struct PomExactArgs {
+    const void* vol;
+    uint8_t* pdms;
+    int64_t G;
+    int nx, ny, nz, Bx, By, Bz, bytes, n, levels;
+    int vec_ok, store_vec;
+};
+
 hipError_t launch_bricks(const BrickArgs& a, hipStream_t s);
 hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
+hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
+hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
 hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
                           int vec, hipStream_t s);

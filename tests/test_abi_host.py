@@ -131,3 +131,18 @@ def test_active_set_matches_oracle(orc):
 def test_binding_rejects_wrong_alpha_length():
     with pytest.raises(ValueError):
         L.active_set(W.uniform_bounds(256, 8), np.zeros(255, np.float32), 256)
+
+
+def test_exact_calls_reject_unsupported_sizes(lib):
+    r = ctypes.byref
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    wide = desc(nx=4 * 257)                       # 257 bricks along x
+    assert lib.pdm_build_partitions_exact(r(wide), FAKE, pb, 8, FAKE, NULL) == L.PDM_E_UNSUPPORTED
+    big = desc(dtype=2, levels=16385)
+    bnd2, pb2 = _b(W.uniform_bounds(16385, 8))
+    assert lib.pdm_build_partitions_exact(r(big), FAKE, pb2, 8, FAKE, NULL) == L.PDM_E_UNSUPPORTED
+    alpha = np.ones(16385, np.float32)
+    assert lib.pdm_full_recompute_exact(r(big), FAKE, ctypes.c_void_p(alpha.ctypes.data), FAKE,
+                                        NULL) == L.PDM_E_UNSUPPORTED
+    assert lib.pdm_build_partitions_exact(r(desc()), NULL, pb, 8, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute_exact(r(desc()), FAKE, NULL, FAKE, NULL) == L.PDM_E_INVAL

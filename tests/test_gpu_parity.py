@@ -197,3 +197,73 @@ def test_invalid_arguments_raise(pdm):
         v.update_tf(np.zeros(100, np.float32))
     with pytest.raises(ValueError):
         pdm.tf_update(v.desc, v.pdms[:2], v.bounds, np.zeros(256, np.float32), v.dist)
+
+
+# ------------------------------------------------------- EXACT occupancy
+def run_exact(pdm, orc, vol, levels, bounds, alphas, label):
+    import torch
+    say(f"[case] EXACT {label}: shape={vol.shape} dtype={vol.dtype} L={levels} n={len(bounds) - 1}")
+    v = pdm.Volume(pdm.to_device(vol), levels, bounds, voxel_dtype=vol.dtype, mode=pdm.EXACT)
+    v.build()
+    torch.cuda.synchronize()
+    want = orc.pdms(vol, bounds, levels, mode=orc.EXACT)
+    np.testing.assert_array_equal(pdm.from_device(v.pdms), want)
+    d = torch.empty_like(v.dist)
+    for k, alpha in enumerate(alphas):
+        mask = v.update_tf(alpha)
+        v.full_recompute(alpha, out=d)
+        torch.cuda.synchronize()
+        dp, m = orc.tf_update(want, bounds, alpha, levels)
+        np.testing.assert_array_equal(mask, m)
+        np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"D' tf {k}")
+        np.testing.assert_array_equal(pdm.from_device(d),
+                                      orc.full_recompute(vol, alpha, levels, mode=orc.EXACT),
+                                      err_msg=f"D tf {k}")
+
+
+EXACT_SHAPES = [
+    ((1, 1, 1), np.uint8, 256, 4, "single voxel"),
+    ((17, 9, 13), np.uint8, 256, 16, "ragged u8"),
+    ((23, 18, 30), np.uint16, 4096, 32, "ragged u16 12-bit"),
+    ((40, 36, 64), np.uint8, 256, 256, "one partition per level"),
+    ((20, 24, 40), np.uint16, 4096, 100, "u16, 100 partitions"),
+    ((9, 14, 1024), np.uint8, 256, 64, "x rows of 256 bricks"),
+    ((3, 1030, 6), np.uint8, 256, 3, "y lines over 256 bricks"),
+    ((64, 64, 68), np.uint8, 256, 8, "x not a multiple of 16"),
+]
+
+
+@pytest.mark.parametrize("shape,dtype,levels,n,label", EXACT_SHAPES, ids=[s[-1] for s in EXACT_SHAPES])
+def test_exact_shapes(pdm, orc, shape, dtype, levels, n, label):
+    # noisier than `blocky`: bricks mix several intensities, so EXACT and
+    # RANGE occupancy differ
+    rng = np.random.default_rng(sum(shape) + n)
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + n)
+    noise = rng.integers(0, levels, size=shape).astype(dtype)
+    vol = np.where(rng.random(shape) < 0.05, noise, vol).astype(dtype)
+    run_exact(pdm, orc, vol, levels, W.uniform_bounds(levels, n), tfs(levels, 5, sum(shape)), label)
+
+
+def test_exact_config1_and_rhomin(pdm, orc):
+    vol = W.make_volume("c1")
+    run_exact(pdm, orc, vol, 256, W.uniform_bounds(256, 8), W.make_tfs("c1") + tfs(256, 10, 3), "c1")
+    run_exact(pdm, orc, vol, 256, W.rhomin_bounds(256, 16, 2), tfs(256, 4, 4), "c1 rho_min")
+
+
+def test_exact_within_range(pdm, orc):
+    """EXACT occupancy is contained in RANGE occupancy, so EXACT distances are
+    element-wise >= RANGE distances, for PDMs and for D."""
+    import torch
+    vol = W.make_volume("c1")
+    bounds = W.uniform_bounds(256, 8)
+    vr = pdm.Volume(pdm.to_device(vol), 256, bounds)
+    ve = pdm.Volume(pdm.to_device(vol), 256, bounds, mode=pdm.EXACT)
+    vr.build()
+    ve.build()
+    torch.cuda.synchronize()
+    assert bool((ve.pdms >= vr.pdms).all().item())
+    alpha = W.make_tfs("c1")[0]
+    vr.full_recompute(alpha)
+    ve.full_recompute(alpha)
+    torch.cuda.synchronize()
+    assert bool((ve.dist >= vr.dist).all().item())
