@@ -19,6 +19,13 @@ oracle timed on a slab of the same volume (see `cpu_baseline()`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
                        [--no-cpu-baseline] [--calib-copy-mib M]
+                       [--workload tube_tree|batched]
+
+--workload batched: 48 volumes of uneven sizes (96-640 per axis, half u8 and
+half 12-bit u16, 16/32/64 partitions).  Times the one-launch persistent build
+(launch shape from the autotuner) against a per-volume launch loop, and the
+one-launch TF update of all 48 volumes (a different TF each) against a
+per-volume loop; checks that both ways give identical bytes.
 """
 from __future__ import annotations
 
@@ -128,6 +135,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
+    ap.add_argument("--workload", default="tube_tree", choices=("tube_tree", "batched"))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -141,6 +149,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        run_batched(args)
+        return
     cfg = W.config_info("c3")
     L, n = cfg["levels"], cfg["n"]
     log("generating tube-tree 1024x1024x795 u8 ...")
@@ -293,6 +304,104 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a slab ...")
         out["cpu_baseline"] = cpu_baseline(vol, bounds, alphas, L, step_bytes)
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """48 uneven volumes: persistent batched build and one-launch TF update
+    against per-volume launch loops."""
+    import torch
+    import paper_2407_21552_amd as pdm
+    from paper_2407_21552_amd import autotune
+    import workloads as W
+
+    specs = W.batch_specs()
+    vols, alphas = [], []
+    log("generating and uploading 48 volumes ...")
+    for k, sp in enumerate(specs):
+        vol = W.batch_volume(sp)
+        bounds = W.uniform_bounds(sp["levels"], sp["n"])
+        v = pdm.Volume(pdm.to_device(vol), sp["levels"], bounds, voxel_dtype=sp["dtype"])
+        vols.append(v)
+        rng = np.random.default_rng(40_000 + k)
+        alphas.append(W.trapezoid_tf(sp["levels"], int(rng.integers(1, 5)), rng))
+        del vol
+    stream = torch.cuda.current_stream()
+    items = [(v.desc, v.volume, v.bmin, v.bmax, v.bounds, v.pdms) for v in vols]
+    ws = torch.zeros(pdm.batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    def loop_build():
+        for v in vols:
+            pdm.build_bricks(v.desc, v.volume, v.bmin, v.bmax, None, stream)
+            pdm.build_partitions(v.desc, v.bmin, v.bmax, v.bounds, v.pdms, stream)
+
+    log("per-volume build loop ...")
+    loop_ms = timed(loop_build, args.steps)
+    ref = [v.pdms.clone() for v in vols]
+    log("autotuning the batched build ...")
+    best, table = autotune.tune_batch_build(items, ws, reps=3, cache_path=None, stream=stream)
+    for v in vols:
+        v.pdms.fill_(0)
+    batch_ms = timed(lambda: pdm.batch_build(items, ws, best, stream), args.steps)
+    assert pdm.batch_error(ws) == 0, "batched build failed"
+    same_build = all(bool(torch.equal(a, v.pdms)) for a, v in zip(ref, vols))
+    default_ms = timed(lambda: pdm.batch_build(items, ws, None, stream), args.steps)
+
+    outs_loop = [torch.empty_like(v.dist) for v in vols]
+    outs_batch = [torch.empty_like(v.dist) for v in vols]
+
+    def loop_update():
+        for v, a, o in zip(vols, alphas, outs_loop):
+            pdm.tf_update(v.desc, v.pdms, v.bounds, a, o, stream)
+
+    upd_items = [(v.desc, v.pdms, v.bounds, a, o) for v, a, o in zip(vols, alphas, outs_batch)]
+    log("TF updates: per-volume loop vs one launch ...")
+    upd_loop_ms = timed(loop_update, 20)
+    masks = pdm.batch_tf_update(upd_items, stream)
+    upd_batch_ms = timed(lambda: pdm.batch_tf_update(upd_items, stream), 20)
+    same_update = all(bool(torch.equal(a, b)) for a, b in zip(outs_loop, outs_batch))
+
+    G_tot = sum(v.G for v in vols)
+    vox_bytes = sum(v.volume.numel() * v.volume.element_size() for v in vols)
+    build_bytes = sum(v.volume.numel() * v.volume.element_size() + 4 * v.G * v.voxel_dtype.itemsize
+                      + v.n * v.G for v in vols)
+    upd_bytes = sum((len(pdm.mask_to_list(m, v.n)) + 1) * v.G for m, v in zip(masks, vols))
+    out = {
+        "metric": "batched build and TF update of 48 uneven volumes (ms), one launch vs per-volume loop",
+        "value": round(upd_bytes / (upd_batch_ms * 1e-3) / 1e9, 1),
+        "unit": "GB/s (batched TF update)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic (48 seeded volumes: ellipsoid u8 and CT-like 12-bit u16)",
+        "config": {"workload": "48 volumes, dims U{96..640}, half u8 / half u16 (12-bit), "
+                               "partitions from {16,32,64}, bricks 4^3",
+                   "volumes": len(vols), "voxels_bytes": vox_bytes, "bricks_total": G_tot,
+                   "pdm_bytes": sum(v.n * v.G for v in vols)},
+        "build": {"per_volume_loop_ms": round(loop_ms, 3), "batched_tuned_ms": round(batch_ms, 3),
+                  "batched_default_ms": round(default_ms, 3),
+                  "speedup_vs_loop": round(loop_ms / batch_ms, 3),
+                  "GBps_batched": round(build_bytes / (batch_ms * 1e-3) / 1e9, 1),
+                  "tuned_config": best, "identical_to_loop": same_build,
+                  "autotune_table_ms": {k: round(t, 3) for k, t in sorted(table.items(), key=lambda kv: kv[1])}},
+        "tf_update": {"per_volume_loop_ms": round(upd_loop_ms, 4), "batched_ms": round(upd_batch_ms, 4),
+                      "speedup_vs_loop": round(upd_loop_ms / upd_batch_ms, 3),
+                      "GBps_batched": round(upd_bytes / (upd_batch_ms * 1e-3) / 1e9, 1),
+                      "identical_to_loop": same_update},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -131,6 +131,63 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
 pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                               uint8_t* d_dist, hipStream_t stream);
 
+/* Batched TF update: the update of pdm_tf_update for up to PDM_BATCH_MAX
+ * volumes, each with its own PDMs, partitions, opacity table and output, in
+ * one kernel launch (the step a server runs per tick).  h_items: `count`
+ * descriptors (host, read during the call); every volume is validated as in
+ * pdm_tf_update before anything is launched.  Outputs must not overlap.
+ * h_active: nullable, 4 words per item (the S masks, item-major). */
+#define PDM_BATCH_MAX 48
+typedef struct {
+    const pdm_volume* v;     /* geometry and levels of the volume */
+    const uint8_t* d_pdms;   /* n*G bytes */
+    const int32_t* h_bounds; /* n+1 partition borders */
+    int32_t n;               /* partitions */
+    const float* h_alpha;    /* v->levels entries */
+    uint8_t* d_dist;         /* G bytes: D' */
+} pdm_batch_update;
+
+pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
+                               uint64_t* h_active, hipStream_t stream);
+
+/* Batched one-time initialisation: pdm_build_bricks + pdm_build_partitions
+ * for up to PDM_BATCH_MAX volumes of different sizes, dtypes and partition
+ * counts in ONE persistent kernel launch fed from a device work queue
+ * (bricks and x distances per z slice, then y passes, then z passes; each
+ * volume's next phase starts when its previous phase is done).  Results are
+ * identical to the single-volume calls.  Every grid axis must be <= 256
+ * bricks (else PDM_E_UNSUPPORTED).
+ *
+ * d_workspace: device memory of pdm_batch_workspace_bytes(count) bytes,
+ * 16-byte aligned, owned by the caller, not used by any other call until the
+ * build is done.  Its first 8 bytes are two uint32 words {next ticket,
+ * error}: after the stream completes, error != 0 means a work item gave up
+ * waiting (never expected; the outputs are then incomplete).
+ * cfg: nullable tuning knobs (see pdm_batch_config); results do not depend on
+ * them. */
+typedef struct {
+    const pdm_volume* v;     /* geometry and levels */
+    const void* d_volume;    /* voxels */
+    void* d_bmin;            /* G elements of v->dtype */
+    void* d_bmax;            /* G elements of v->dtype */
+    const int32_t* h_bounds; /* n+1 partition borders */
+    int32_t n;               /* partitions */
+    uint8_t* d_pdms;         /* n*G bytes */
+} pdm_batch_volume;
+
+typedef struct {
+    int32_t waves;          /* resident one-wave work-groups; 0 = 8 per compute unit */
+    int32_t lines_mult;     /* 64-line groups per y/z work item, 1..16; 0 = 1 */
+    int32_t largest_first;  /* 1: hand out the largest volumes' items first */
+    int32_t reserved;
+} pdm_batch_config;
+
+size_t pdm_batch_workspace_bytes(int32_t count);
+
+pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
+                           size_t workspace_bytes, const pdm_batch_config* cfg,
+                           hipStream_t stream);
+
 /* EXACT occupancy reading (Sec. 3.1, literal wording): a brick is occupied
  * for an intensity interval when one of its voxels lies in it (for the plain
  * method: when one of its voxels has non-zero opacity), instead of the RANGE

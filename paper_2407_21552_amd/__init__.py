@@ -16,13 +16,16 @@ from __future__ import annotations
 import numpy as np
 
 from . import _lib
-from ._lib import (BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, active_set, build_bricks,
+from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, active_set,
+                   batch_build, batch_error, batch_tf_update, batch_workspace_bytes, build_bricks,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
                    full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
                    volume_desc)
 
-__all__ = ["Volume", "PdmError", "active_set", "build_bricks", "build_partitions",
+__all__ = ["Volume", "PdmError", "active_set", "batch_build", "batch_error", "batch_tf_update",
+           "batch_workspace_bytes", "BATCH_MAX", "build_bricks",
+           "build_partitions",
            "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
            "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
            "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",

@@ -36,6 +36,27 @@ class VolumeDesc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("levels", ctypes.c_int32), ("brick", ctypes.c_int32)]
 
 
+class BatchUpdate(ctypes.Structure):
+    _fields_ = [("v", ctypes.POINTER(VolumeDesc)), ("d_pdms", ctypes.c_void_p),
+                ("h_bounds", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("h_alpha", ctypes.c_void_p), ("d_dist", ctypes.c_void_p)]
+
+
+BATCH_MAX = 48
+
+
+class BatchVolume(ctypes.Structure):
+    _fields_ = [("v", ctypes.POINTER(VolumeDesc)), ("d_volume", ctypes.c_void_p),
+                ("d_bmin", ctypes.c_void_p), ("d_bmax", ctypes.c_void_p),
+                ("h_bounds", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("d_pdms", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("lines_mult", ctypes.c_int32),
+                ("largest_first", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class GridDesc(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
                 ("count", ctypes.c_int64)]
@@ -67,11 +88,16 @@ def lib() -> ctypes.CDLL:
         L.pdm_pom_exact_distance_x.argtypes = [V, P, P, i32, P, P]
         L.pdm_full_recompute_exact.argtypes = [V, P, P, P, P]
         L.pdm_plain_exact_distance_x.argtypes = [V, P, P, P, P]
+        L.pdm_batch_tf_update.argtypes = [ctypes.POINTER(BatchUpdate), i32, P, P]
+        L.pdm_batch_workspace_bytes.argtypes = [i32]
+        L.pdm_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.pdm_batch_build.argtypes = [ctypes.POINTER(BatchVolume), i32, P, ctypes.c_size_t,
+                                      ctypes.POINTER(BatchConfig), P]
         for name in ("pdm_grid_of", "pdm_active_set", "pdm_build_bricks", "pdm_build_partitions",
                      "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
                      "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
                      "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
-                     "pdm_plain_exact_distance_x"):
+                     "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build"):
             getattr(L, name).restype = st
         L.pdm_status_string.argtypes = [st]
         L.pdm_status_string.restype = ctypes.c_char_p
@@ -283,3 +309,78 @@ def plain_exact_distance_x(desc, volume, alpha, dist, stream=None) -> None:
                                             _dev_ptr(volume, _vox_bytes(desc), "volume"),
                                             _np_ptr(a), _dev_ptr(dist, G, "dist"),
                                             _stream(stream)), "pdm_plain_exact_distance_x")
+
+
+# ------------------------------------------------------------ batched update
+def batch_tf_update(items, stream=None) -> np.ndarray:
+    """TF updates of several volumes in one launch.  items: sequence of
+    (desc, pdms, bounds, alpha, dist).  Returns the S masks, shape (count, 4)."""
+    count = len(items)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
+    arr = (BatchUpdate * count)()
+    keep = []
+    for k, (desc, pdms, bounds, alpha, dist) in enumerate(items):
+        G = grid_of(desc)[3]
+        b = _bounds(bounds)
+        n = len(b) - 1
+        a = _alpha(alpha, desc.levels)
+        keep += [desc, b, a]
+        arr[k].v = ctypes.pointer(desc)
+        arr[k].d_pdms = _dev_ptr(pdms, n * G, "pdms")
+        arr[k].h_bounds = _np_ptr(b)
+        arr[k].n = n
+        arr[k].h_alpha = _np_ptr(a)
+        arr[k].d_dist = _dev_ptr(dist, G, "dist")
+    masks = np.zeros((count, 4), np.uint64)
+    _check(lib().pdm_batch_tf_update(arr, count, _np_ptr(masks), _stream(stream)),
+           "pdm_batch_tf_update")
+    del keep
+    return masks
+
+
+# ------------------------------------------------------------- batched build
+def batch_workspace_bytes(count: int) -> int:
+    return int(lib().pdm_batch_workspace_bytes(int(count)))
+
+
+def batch_build(items, workspace, config=None, stream=None) -> None:
+    """One persistent launch building bricks and PDMs of several volumes.
+    items: sequence of (desc, volume, bmin, bmax, bounds, pdms); workspace: a
+    uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more;
+    config: None or dict(waves=, lines_mult=, largest_first=)."""
+    count = len(items)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
+    arr = (BatchVolume * count)()
+    keep = []
+    for k, (desc, volume, bmin, bmax, bounds, pdms) in enumerate(items):
+        G = grid_of(desc)[3]
+        b = _bounds(bounds)
+        n = len(b) - 1
+        keep += [desc, b]
+        arr[k].v = ctypes.pointer(desc)
+        arr[k].d_volume = _dev_ptr(volume, _vox_bytes(desc), "volume")
+        arr[k].d_bmin = _dev_ptr(bmin, G * desc.dtype, "bmin")
+        arr[k].d_bmax = _dev_ptr(bmax, G * desc.dtype, "bmax")
+        arr[k].h_bounds = _np_ptr(b)
+        arr[k].n = n
+        arr[k].d_pdms = _dev_ptr(pdms, n * G, "pdms")
+    need = batch_workspace_bytes(count)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    if ws_bytes < need:
+        raise ValueError(f"workspace holds {ws_bytes} bytes, needs {need}")
+    cfg = None
+    if config is not None:
+        cfg = ctypes.pointer(BatchConfig(int(config.get("waves", 0)),
+                                         int(config.get("lines_mult", 0)),
+                                         int(config.get("largest_first", 0)), 0))
+    _check(lib().pdm_batch_build(arr, count, _dev_ptr(workspace, ws_bytes, "workspace"),
+                                 ws_bytes, cfg, _stream(stream)), "pdm_batch_build")
+    del keep
+
+
+def batch_error(workspace) -> int:
+    """The error word of a batch-build workspace (synchronises)."""
+    import torch
+    return int(workspace[4:8].view(torch.int32).item())

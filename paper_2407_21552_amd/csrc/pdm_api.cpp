@@ -202,6 +202,117 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
     return from_hip(pdm::launch_combine(d_pdms, g.count, act, d_dist, vec, stream));
 }
 
+pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
+                               uint64_t* h_active, hipStream_t stream) {
+    if (h_items == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
+    static_assert(PDM_BATCH_MAX <= PDM_BATCH_MAX_ITEMS, "batch descriptors exceed kernel arguments");
+    pdm::BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.count = count;
+    for (int32_t k = 0; k < count; ++k) {
+        const pdm_batch_update& it = h_items[k];
+        pdm_grid g;
+        pdm_status st = check_volume(it.v, &g);
+        if (st != PDM_OK) return st;
+        if (it.d_pdms == nullptr || it.d_dist == nullptr || it.h_alpha == nullptr) return PDM_E_INVAL;
+        st = check_bounds(it.h_bounds, it.n, it.v->levels);
+        if (st != PDM_OK) return st;
+        pdm::BatchItem& b = a.it[k];
+        active_mask(it.h_bounds, it.n, it.h_alpha, b.mask);
+        if (h_active != nullptr)
+            for (int w = 0; w < 4; ++w) h_active[4 * k + w] = b.mask[w];
+        b.pdms = it.d_pdms;
+        b.out = it.d_dist;
+        b.G = g.count;
+        b.vec16 = g.count % 16 == 0 && aligned(it.d_pdms, 16) && aligned(it.d_dist, 16);
+    }
+    return from_hip(pdm::launch_batch_combine(a, stream));
+}
+
+size_t pdm_batch_workspace_bytes(int32_t count) {
+    if (count < 1 || count > PDM_BATCH_MAX) return 0;
+    return sizeof(pdm::BatchState) + 16 + (size_t)count * sizeof(pdm::BatchVol);
+}
+
+pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
+                           size_t workspace_bytes, const pdm_batch_config* cfg,
+                           hipStream_t stream) {
+    if (h_vols == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
+    if (d_workspace == nullptr || !aligned(d_workspace, 16) ||
+        workspace_bytes < pdm_batch_workspace_bytes(count))
+        return PDM_E_INVAL;
+    pdm_batch_config c = {0, 1, 0, 0};
+    if (cfg != nullptr) c = *cfg;
+    if (c.waves < 0 || c.lines_mult < 0 || c.lines_mult > 16) return PDM_E_INVAL;
+    if (c.lines_mult == 0) c.lines_mult = 1;
+    if (c.waves == 0) c.waves = 8 * 256;
+    static_assert(PDM_BATCH_MAX <= PDM_BATCH_MAX_ITEMS, "batch descriptors exceed the state");
+    // host staging of the descriptors (copied to the workspace by the launcher)
+    pdm::BatchVol tmp[PDM_BATCH_MAX];
+    pdm::BatchVol vols[PDM_BATCH_MAX];
+    int64_t work[PDM_BATCH_MAX];
+    for (int32_t k = 0; k < count; ++k) {
+        const pdm_batch_volume& it = h_vols[k];
+        pdm_grid g;
+        pdm_status st = check_volume(it.v, &g);
+        if (st != PDM_OK) return st;
+        if (it.d_volume == nullptr || it.d_bmin == nullptr || it.d_bmax == nullptr ||
+            it.d_pdms == nullptr)
+            return PDM_E_INVAL;
+        st = check_bounds(it.h_bounds, it.n, it.v->levels);
+        if (st != PDM_OK) return st;
+        if (g.bx > 256 || g.by > 256 || g.bz > 256) return PDM_E_UNSUPPORTED;
+        pdm::BatchVol& d = tmp[k];
+        memset(&d, 0, sizeof(d));
+        d.vol = it.d_volume;
+        d.bmin = it.d_bmin;
+        d.bmax = it.d_bmax;
+        d.pdms = it.d_pdms;
+        d.G = g.count;
+        d.nx = it.v->nx;
+        d.ny = it.v->ny;
+        d.nz = it.v->nz;
+        d.Bx = g.bx;
+        d.By = g.by;
+        d.Bz = g.bz;
+        d.bytes = it.v->dtype;
+        d.n = it.n;
+        d.levels = it.v->levels;
+        d.vec_ok = ((int64_t)it.v->nx * it.v->dtype) % 16 == 0 && aligned(it.d_volume, 16);
+        d.store_vec = g.bx % 4 == 0 && aligned(it.d_pdms, 4);
+        for (int32_t p = 0; p <= it.n; ++p) d.bounds[p] = it.h_bounds[p];
+        const int64_t lines = (int64_t)it.n * g.bx;
+        d.chunks = (int32_t)((lines + 64 * c.lines_mult - 1) / (64 * c.lines_mult));
+        d.items[0] = g.bz;
+        d.items[1] = g.bz * d.chunks;
+        d.items[2] = g.by * d.chunks;
+        work[k] = (int64_t)it.n * g.count;
+    }
+    // hand-out order of the volumes (the same in every phase)
+    int32_t order[PDM_BATCH_MAX];
+    for (int32_t k = 0; k < count; ++k) order[k] = k;
+    if (c.largest_first)
+        for (int32_t a = 1; a < count; ++a)
+            for (int32_t b = a; b > 0 && work[order[b]] > work[order[b - 1]]; --b) {
+                const int32_t t = order[b];
+                order[b] = order[b - 1];
+                order[b - 1] = t;
+            }
+    for (int32_t k = 0; k < count; ++k) vols[k] = tmp[order[k]];
+    int64_t t = 0;
+    for (int ph = 0; ph < 3; ++ph)
+        for (int32_t k = 0; k < count; ++k) {
+            vols[k].first[ph] = t;
+            t += vols[k].items[ph];
+        }
+    if (t > INT32_MAX) return PDM_E_UNSUPPORTED;
+    uint8_t* ws = static_cast<uint8_t*>(d_workspace);
+    pdm::BatchState* state = reinterpret_cast<pdm::BatchState*>(ws);
+    pdm::BatchVol* dv = reinterpret_cast<pdm::BatchVol*>(ws + ((sizeof(pdm::BatchState) + 15) & ~(size_t)15));
+    return from_hip(pdm::launch_batch_build(vols, count, dv, state, t, c.waves, 1u << 24,
+                                            c.lines_mult, stream));
+}
+
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                                 uint8_t* d_dist, hipStream_t stream) {
     pdm::PlainArgs a;

@@ -18,11 +18,13 @@
 //   k_dist_axis     x distances -> full chessboard distances: 1-D max-min pass
 //                   along y or z, one lane per line, linear-time scan.
 //   k_combine       masked min over the active PDM streams, 16 bytes per lane.
+//   k_batch_combine the TF updates of up to 48 volumes in one launch.
 //   k_pom_exact_x   EXACT reading: per-brick partition masks from the voxels,
 //                   then the x distances of every partition.
 //   k_plain_exact_x EXACT reading of the plain method's occupancy.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "pdm_launch.h"
 
@@ -843,6 +845,215 @@ __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdm
 }
 
 // ---------------------------------------------------------------------------
+// k_batch_combine: the TF update of many volumes in one launch.  Each volume
+// has its own PDM stack, output map and active set (a 256-bit mask); blocks
+// are assigned to volumes by the prefix counts in first_block, so every
+// work-group serves one volume.  A lane owns 16 consecutive bricks; volumes
+// whose size or pointers are not 16-byte aligned take a byte-wise path.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
+    int k = 0;
+    while (k + 1 < a.count && (int64_t)blockIdx.x >= a.it[k + 1].first_block) ++k;
+    const uint8_t* __restrict__ pdms = a.it[k].pdms;
+    uint8_t* __restrict__ out = a.it[k].out;
+    const int64_t G = a.it[k].G;
+    const int64_t off = (((int64_t)blockIdx.x - a.it[k].first_block) * blockDim.x + threadIdx.x) * 16;
+    if (off >= G) return;
+    if (a.it[k].vec16) {
+        uint32_t e[4], o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] = o[j] = 0x00FF00FFu;
+        for (int w = 0; w < 4; ++w) {
+            uint64_t m = a.it[k].mask[w];
+            while (m) {
+                const int p = 64 * w + (__ffsll((unsigned long long)m) - 1);
+                m &= m - 1;
+                min_bytes16(e, o, load_nt16(pdms + (int64_t)p * G + off));
+            }
+        }
+        uint4 r;
+        r.x = e[0] | (o[0] << 8);
+        r.y = e[1] | (o[1] << 8);
+        r.z = e[2] | (o[2] << 8);
+        r.w = e[3] | (o[3] << 8);
+        *reinterpret_cast<uint4*>(out + off) = r;
+    } else {
+        const int nb = (int)min((int64_t)16, G - off);
+        uint32_t mm[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) mm[j] = 255u;
+        for (int w = 0; w < 4; ++w) {
+            uint64_t m = a.it[k].mask[w];
+            while (m) {
+                const int p = 64 * w + (__ffsll((unsigned long long)m) - 1);
+                m &= m - 1;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (j < nb) mm[j] = umin(mm[j], (uint32_t)pdms[(int64_t)p * G + off + j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < nb) out[off + j] = (uint8_t)mm[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_batch_build: the one-time initialisation of many volumes in one
+// persistent launch.  Work items are handed out in order from a device
+// ticket counter:
+//   phase 0  (volume, z slice): brick [min,max] of every row of the slice,
+//            then every partition's POM row and x distances (bricks + POM x
+//            fused: the volume is read once);
+//   phase 1  (volume, z slice, 64-line chunk): y pass of lines (p, z, x);
+//   phase 2  (volume, y row, 64-line chunk): z pass of lines (p, y, x).
+// All phase-0 tickets come before all phase-1 tickets and those before all
+// phase-2 tickets.  A phase-1 (2) item of volume v waits until every phase-0
+// (1) item of v is done; those hold smaller tickets, taken earlier by running
+// work-groups, so the wait always ends.  Each wait is still bounded: after
+// spin_limit polls the work-group sets the error flag and stops, so every
+// wave exits.  Completion: the wave's stores are released at agent scope
+// before its counter increment; waiters acquire at agent scope (the L2s of
+// the XCDs are not coherent with each other).  One wave per work-group.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool wait_done(const uint32_t* cnt, uint32_t target, uint32_t* err,
+                                          uint32_t spin_limit) {
+    uint32_t ok = 1;
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > spin_limit ||
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        if (!ok) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ok = (uint32_t)__shfl((int)ok, 0, kWave);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0u;
+}
+
+__device__ __forceinline__ void mark_done(uint32_t* cnt) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Phase 0 for one z slice of one volume (Bx <= 256: one segment per row).
+template <typename T>
+__device__ __forceinline__ void batch_rows(const BatchVol& d, int bz) {
+    const int lane = threadIdx.x;
+    const T* vol = reinterpret_cast<const T*>(d.vol);
+    T* bmin = reinterpret_cast<T*>(d.bmin);
+    T* bmax = reinterpret_cast<T*>(d.bmax);
+    const int nb = max(0, min(4, d.Bx - 4 * lane));
+    for (int by = 0; by < d.By; ++by) {
+        const int64_t rbase = ((int64_t)bz * d.By + by) * d.Bx;
+        uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        uint32_t mx[4] = {0u, 0u, 0u, 0u};
+        if (nb > 0) {
+            const QuadMinMax<T> r = quad_minmax<T>(vol, d.nx, d.ny, d.nz, lane, by, bz, d.vec_ok != 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < nb) {
+                    mn[k] = r.mn[k];
+                    mx[k] = r.mx[k];
+                    bmin[rbase + 4 * lane + k] = (T)r.mn[k];
+                    bmax[rbase + 4 * lane + k] = (T)r.mx[k];
+                }
+        }
+        for (int p = 0; p < d.n; ++p) {
+            const uint32_t lo = (uint32_t)d.bounds[p], hi = (uint32_t)d.bounds[p + 1] - 1u;
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
+            if (nb > 0) store_quad(d.pdms + (int64_t)p * d.G, rbase + 4 * lane, nb, packed, d.store_vec);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_batch_build(const BatchVol* __restrict__ vols, int count,
+                                                       BatchState* __restrict__ st, int64_t total,
+                                                       uint32_t spin_limit, int lines_mult) {
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int64_t t = 0;
+        if (lane == 0) t = (int64_t)__hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+        t = (int64_t)__shfl((int)t, 0, kWave);
+        if (t >= total) break;
+        if (__hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        // locate (phase, volume) of ticket t
+        int ph = 2;
+        while (ph > 0 && t < vols[0].first[ph]) --ph;
+        int v = count - 1;
+        while (v > 0 && t < vols[v].first[ph]) --v;
+        const BatchVol& d = vols[v];
+        const int64_t local = t - d.first[ph];
+        if (ph == 0) {
+            if (d.bytes == 1)
+                batch_rows<uint8_t>(d, (int)local);
+            else
+                batch_rows<uint16_t>(d, (int)local);
+            mark_done(&st->done[0][v]);
+            continue;
+        }
+        if (!wait_done(&st->done[ph - 1][v], (uint32_t)d.items[ph - 1], &st->error, spin_limit)) break;
+        const int outer = (int)(local / d.chunks);  // z slice (phase 1) or y row (phase 2)
+        for (int j = 0; j < lines_mult; ++j) {
+            // (p, x) lines of this slice or row, 64 per pass of the wave
+            const int64_t line = ((local % d.chunks) * lines_mult + j) * kWave + lane;
+            const bool active = line < (int64_t)d.n * d.Bx;
+            const int p = active ? (int)(line / d.Bx) : 0;
+            const int x = active ? (int)(line % d.Bx) : 0;
+            int64_t base, stride;
+            int m;
+            if (ph == 1) {
+                base = (int64_t)p * d.G + (int64_t)outer * d.Bx * d.By + x;
+                stride = d.Bx;
+                m = d.By;
+            } else {
+                base = (int64_t)p * d.G + (int64_t)outer * d.Bx + x;
+                stride = (int64_t)d.Bx * d.By;
+                m = d.Bz;
+            }
+            if (m > 1) {
+                uint8_t* q = d.pdms + (active ? base : 0);
+                clear_table<uint8_t>(tbl);
+                __builtin_amdgcn_wave_barrier();
+                one_sided_global<uint8_t, 16>(q, stride, m, active, tbl);
+                __builtin_amdgcn_wave_barrier();
+                clear_table<uint8_t>(tbl);
+                __builtin_amdgcn_wave_barrier();
+                one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
+            }
+        }
+        mark_done(&st->done[ph][v]);
+    }
+}
+
+// Copies descriptor bytes carried in kernel arguments to device memory and
+// zeroes the build state; run before k_batch_build on the same stream.
+struct UploadChunk {
+    int32_t bytes;
+    int32_t pad[3];
+    uint4 data[220];  // 3520 bytes
+};
+
+__global__ void __launch_bounds__(256) k_upload(uint8_t* __restrict__ dst, UploadChunk c) {
+    for (int i = threadIdx.x; i < c.bytes / 16; i += blockDim.x)
+        reinterpret_cast<uint4*>(dst)[i] = c.data[i];
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint32_t* __restrict__ p, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers (host side).  Shapes are validated by the caller.
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t threads, int tpb) {
@@ -994,6 +1205,36 @@ hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act,
         k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(pdms, G, act, out);
     else
         k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(pdms, G, act, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
+    int64_t blocks = 0;
+    for (int k = 0; k < a.count; ++k) {
+        a.it[k].first_block = blocks;
+        blocks += ((a.it[k].G + 15) / 16 + 255) / 256;
+    }
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    k_batch_combine<<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
+                              BatchState* d_state, int64_t total, int waves, uint32_t spin_limit,
+                              int lines_mult, hipStream_t s) {
+    static_assert(sizeof(BatchVol) % 16 == 0, "descriptor size");
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(h_vols);
+    const int64_t bytes = (int64_t)count * (int64_t)sizeof(BatchVol);
+    UploadChunk c;
+    for (int64_t off = 0; off < bytes; off += (int64_t)sizeof(c.data)) {
+        const int64_t nb = bytes - off < (int64_t)sizeof(c.data) ? bytes - off : (int64_t)sizeof(c.data);
+        c.bytes = (int32_t)nb;
+        memcpy(c.data, src + off, (size_t)nb);
+        k_upload<<<1, 256, 0, s>>>(reinterpret_cast<uint8_t*>(d_vols) + off, c);
+    }
+    k_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(d_state), (int)(sizeof(BatchState) / 4));
+    k_batch_build<<<(unsigned)waves, kWave, 0, s>>>(d_vols, count, d_state, total, spin_limit,
+                                                     lines_mult);
     return hipGetLastError();
 }
 

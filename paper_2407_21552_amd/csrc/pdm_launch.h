@@ -7,6 +7,7 @@
 #define PDM_PLAIN_MAX_SEGS 64    // x segments of 256 bricks: Bx <= 16384
 #define PDM_ALPHA_WORDS 512      // non-zero opacity bitmap: levels <= 16384
 #define PDM_EXACT_MAX_LEVELS 16384  // intensity -> partition table of the EXACT build
+#define PDM_BATCH_MAX_ITEMS 48     // volumes per batched TF update (kernel-argument space)
 
 
 namespace pdm {
@@ -25,6 +26,45 @@ struct ActiveList {
 // Bit i set when alpha[i] != 0, passed by value.
 struct AlphaBits {
     uint32_t w[PDM_ALPHA_WORDS];
+};
+
+// One volume of a batched TF update (72 bytes), passed by value.
+struct BatchItem {
+    const uint8_t* pdms;
+    uint8_t* out;
+    int64_t G;
+    int64_t first_block;  // first work-group of this volume (set by the launcher)
+    uint64_t mask[4];     // active partitions
+    int32_t vec16;        // G % 16 == 0 and both pointers 16-byte aligned
+    int32_t pad;
+};
+
+struct BatchArgs {
+    int32_t count;
+    int32_t pad;
+    BatchItem it[PDM_BATCH_MAX_ITEMS];
+};
+
+// Persistent batched build: one descriptor per volume in device memory.
+struct BatchVol {
+    const void* vol;
+    void* bmin;
+    void* bmax;
+    uint8_t* pdms;
+    int64_t G;
+    int64_t first[3];  // first ticket of each phase (bricks+x, y, z) of this volume
+    int32_t items[3];  // tickets per phase
+    int32_t chunks;    // items per slice (y) or row (z): ceil(n*Bx / (64*lines_mult))
+    int32_t nx, ny, nz, Bx, By, Bz, bytes, n, levels, vec_ok, store_vec, pad;
+    int32_t bounds[257];
+    int32_t pad2[3];
+};
+
+// Device workspace of the persistent build, zeroed by the launcher.
+struct BatchState {
+    uint32_t ticket;       // next work item
+    uint32_t error;        // 1 when a wait ran out of spins
+    uint32_t done[3][PDM_BATCH_MAX_ITEMS];  // finished items per phase and volume
 };
 
 struct BrickArgs {
@@ -66,6 +106,13 @@ hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
+hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s);
+// Uploads `count` descriptors into d_vols and zeroes d_state, then runs the
+// persistent build over `total` tickets with `waves` one-wave work-groups;
+// a y/z item covers 64*lines_mult lines.
+hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
+                              BatchState* d_state, int64_t total, int waves, uint32_t spin_limit,
+                              int lines_mult, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
 hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
                           int vec, hipStream_t s);

@@ -146,3 +146,36 @@ def test_exact_calls_reject_unsupported_sizes(lib):
                                         NULL) == L.PDM_E_UNSUPPORTED
     assert lib.pdm_build_partitions_exact(r(desc()), NULL, pb, 8, FAKE, NULL) == L.PDM_E_INVAL
     assert lib.pdm_full_recompute_exact(r(desc()), FAKE, NULL, FAKE, NULL) == L.PDM_E_INVAL
+
+
+def test_batch_update_validates_every_item(lib):
+    d = desc()
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    alpha = np.ones(256, np.float32)
+    good = L.BatchUpdate(ctypes.pointer(d), FAKE, pb, 8, ctypes.c_void_p(alpha.ctypes.data), FAKE)
+    bad_bounds_arr, pbad = _b([0, 100, 100, 256])
+    bad = L.BatchUpdate(ctypes.pointer(d), FAKE, pbad, 3, ctypes.c_void_p(alpha.ctypes.data), FAKE)
+    arr = (L.BatchUpdate * 2)(good, bad)
+    assert lib.pdm_batch_tf_update(arr, 2, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_tf_update(arr, 0, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_tf_update(arr, 49, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_tf_update(None, 1, NULL, NULL) == L.PDM_E_INVAL
+    nod = L.BatchUpdate(ctypes.pointer(d), NULL, pb, 8, ctypes.c_void_p(alpha.ctypes.data), FAKE)
+    assert lib.pdm_batch_tf_update((L.BatchUpdate * 1)(nod), 1, NULL, NULL) == L.PDM_E_INVAL
+
+
+def test_batch_build_validation(lib):
+    d = desc()
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    good = L.BatchVolume(ctypes.pointer(d), FAKE, FAKE, FAKE, pb, 8, FAKE)
+    arr = (L.BatchVolume * 1)(good)
+    need = lib.pdm_batch_workspace_bytes(1)
+    assert need > 0 and lib.pdm_batch_workspace_bytes(0) == 0 and lib.pdm_batch_workspace_bytes(49) == 0
+    assert lib.pdm_batch_build(arr, 1, NULL, need, None, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_build(arr, 1, FAKE, need - 1, None, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_build(arr, 0, FAKE, need, None, NULL) == L.PDM_E_INVAL
+    big = desc(nx=4 * 257)
+    arr2 = (L.BatchVolume * 1)(L.BatchVolume(ctypes.pointer(big), FAKE, FAKE, FAKE, pb, 8, FAKE))
+    assert lib.pdm_batch_build(arr2, 1, FAKE, need, None, NULL) == L.PDM_E_UNSUPPORTED
+    bad_cfg = ctypes.pointer(L.BatchConfig(0, 17, 0, 0))
+    assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_cfg, NULL) == L.PDM_E_INVAL

@@ -267,3 +267,71 @@ def test_exact_within_range(pdm, orc):
     ve.full_recompute(alpha)
     torch.cuda.synchronize()
     assert bool((ve.dist >= vr.dist).all().item())
+
+
+# ----------------------------------------------------- batched TF update
+def test_batch_tf_update_matches_oracle(pdm, orc):
+    """Volumes of mixed dtypes, sizes (ragged, G not a multiple of 16),
+    partition counts and TFs updated in one launch; every D' against the
+    oracle, and against the single-volume call."""
+    import torch
+    rng = np.random.default_rng(31)
+    specs = [((37, 29, 45), np.uint8, 256, 16), ((20, 24, 64), np.uint16, 4096, 32),
+             ((9, 14, 30), np.uint8, 256, 64), ((64, 64, 64), np.uint8, 256, 8),
+             ((5, 6, 7), np.uint16, 4096, 3), ((30, 30, 30), np.uint8, 256, 256)]
+    vols, items, wants = [], [], []
+    for k, (shape, dtype, L, n) in enumerate(specs):
+        vol = blocky(shape, dtype, L, seed=100 + k)
+        bounds = W.uniform_bounds(L, n)
+        v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=dtype)
+        v.build()
+        alpha = W.trapezoid_tf(L, int(rng.integers(1, 4)), rng) if k != 4 else np.zeros(L, np.float32)
+        # an odd offset into a larger buffer: the byte-wise path
+        out = torch.full((v.G + 3,), 7, dtype=torch.uint8, device="cuda")[1:1 + v.G] if k == 2 \
+            else torch.empty(v.G, dtype=torch.uint8, device="cuda")
+        vols.append((v, out))
+        items.append((v.desc, v.pdms, bounds, alpha, out))
+        want_pd = orc.pdms(vol, bounds, L)
+        wants.append(orc.tf_update(want_pd, bounds, alpha, L))
+    say("[case] batch of 6 volumes")
+    masks = pdm.batch_tf_update(items)
+    torch.cuda.synchronize()
+    for k, ((v, out), (dp, m)) in enumerate(zip(vols, wants)):
+        np.testing.assert_array_equal(masks[k], m, err_msg=f"mask {k}")
+        np.testing.assert_array_equal(pdm.from_device(out).reshape(dp.shape), dp, err_msg=f"D' {k}")
+        single = torch.empty_like(v.dist)
+        pdm.tf_update(v.desc, v.pdms, v.bounds, items[k][3], single)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pdm.from_device(single).reshape(-1), pdm.from_device(out))
+
+
+# ------------------------------------------------------ batched build
+@pytest.mark.parametrize("config", [None, dict(waves=64, lines_mult=4, largest_first=1),
+                                    dict(waves=7, lines_mult=1)],
+                         ids=["default", "few-waves-long-items", "seven-waves"])
+def test_batch_build_matches_single_volume_and_oracle(pdm, orc, config):
+    """One persistent launch builds bricks and PDMs of volumes of mixed
+    dtypes, ragged sizes and partition counts; each against the oracle."""
+    import torch
+    specs = [((37, 29, 45), np.uint8, 256, 16), ((20, 24, 64), np.uint16, 4096, 32),
+             ((9, 14, 30), np.uint8, 256, 64), ((64, 64, 64), np.uint8, 256, 8),
+             ((5, 6, 7), np.uint16, 4096, 3), ((1, 1, 1), np.uint8, 256, 2),
+             ((30, 31, 33), np.uint8, 256, 200)]
+    vols, items = [], []
+    for k, (shape, dtype, L, n) in enumerate(specs):
+        vol = blocky(shape, dtype, L, seed=200 + k)
+        bounds = W.uniform_bounds(L, n)
+        v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=dtype)
+        vols.append((vol, v, bounds, L))
+        items.append((v.desc, v.volume, v.bmin, v.bmax, bounds, v.pdms))
+    ws = torch.zeros(pdm.batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+    say(f"[case] batch build of {len(items)} volumes, config {config}")
+    pdm.batch_build(items, ws, config)
+    torch.cuda.synchronize()
+    assert pdm.batch_error(ws) == 0
+    for k, (vol, v, bounds, L) in enumerate(vols):
+        bmin, bmax = orc.bricks(vol)
+        np.testing.assert_array_equal(pdm.from_device(v.bmin, vol.dtype), bmin, err_msg=f"bmin {k}")
+        np.testing.assert_array_equal(pdm.from_device(v.bmax, vol.dtype), bmax, err_msg=f"bmax {k}")
+        np.testing.assert_array_equal(pdm.from_device(v.pdms), orc.pdms(vol, bounds, L),
+                                      err_msg=f"pdms {k}")

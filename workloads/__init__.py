@@ -37,6 +37,7 @@ def _chunk_map(fn, nz: int, seed: int, salt: int):
 __all__ = [
     "CONFIGS", "ellipsoids_u8", "ct_like_u16", "tube_tree_u8", "make_volume",
     "trapezoid_tf", "make_tfs", "uniform_bounds", "rhomin_bounds", "config_info",
+    "batch_specs", "batch_volume",
 ]
 
 # name -> (shape (nz,ny,nx), dtype, levels L, partitions n, volume seed,
@@ -84,8 +85,18 @@ def ellipsoids_u8(shape=(64, 64, 64), seed=1, count=6, semi=(4, 20), value=(30, 
         a = [int(rng.integers(semi[0], semi[1] + 1)) for _ in range(3)]
         v = int(rng.integers(value[0], value[1] + 1))
         _ellipsoid_fill(vol, c, a, v)
-    vol += rng.normal(0.0, sigma, size=shape).astype(np.float32)
-    return np.clip(np.rint(vol), 0, 255).astype(np.uint8)
+    if int(np.prod(shape)) <= (1 << 22):
+        vol += rng.normal(0.0, sigma, size=shape).astype(np.float32)
+        return np.clip(np.rint(vol), 0, 255).astype(np.uint8)
+    out = np.empty(shape, np.uint8)
+
+    def fill(z0, z1, r):
+        sl = vol[z0:z1] + np.float32(sigma) * r.standard_normal(size=vol[z0:z1].shape,
+                                                                  dtype=np.float32)
+        out[z0:z1] = np.clip(np.rint(sl), 0, 255).astype(np.uint8)
+
+    _chunk_map(fill, shape[0], seed, 2)
+    return out
 
 
 def ct_like_u16(shape=(460, 512, 512), seed=2, levels=4096, bones=20, salt=0.05) -> np.ndarray:
@@ -218,6 +229,32 @@ def make_volume(name: str, shape=None) -> np.ndarray:
         vol = tube_tree_u8(shp, c["seed"])
         return vol
     raise KeyError(name)
+
+
+def batch_specs(count: int = 48, seed: int = 4, dims=(96, 640), parts=(16, 32, 64)):
+    """The batched workload: `count` volumes with dims drawn from U{dims} per
+    axis, the first half uint8 (ellipsoid recipe of the 64^3 volume, semi-axes
+    scaled with the volume) and the second half 12-bit in uint16 (CT recipe),
+    partition counts drawn from `parts`.  Returns a list of dicts with shape,
+    dtype, levels, n and seed (volumes are made by batch_volume)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        shape = tuple(int(rng.integers(dims[0], dims[1] + 1)) for _ in range(3))
+        u8 = k < count // 2
+        out.append(dict(shape=shape, dtype=np.uint8 if u8 else np.uint16,
+                        levels=256 if u8 else 4096, n=int(rng.choice(parts)),
+                        seed=10_000 * seed + k))
+    return out
+
+
+def batch_volume(spec: dict) -> np.ndarray:
+    """The volume of one batch_specs entry."""
+    shape = spec["shape"]
+    if spec["dtype"] == np.uint8:
+        scale = min(shape) / 64.0
+        return ellipsoids_u8(shape, spec["seed"], semi=(max(1, int(4 * scale)), max(2, int(20 * scale))))
+    return ct_like_u16(shape, spec["seed"], spec["levels"])
 
 
 def trapezoid_tf(levels: int, ramps: int, rng: np.random.Generator) -> np.ndarray:
