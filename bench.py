@@ -21,6 +21,12 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
                        [--no-cpu-baseline] [--calib-copy-mib M]
                        [--workload tube_tree|batched]
 
+--workload served: a Poisson stream of TF changes (2k/s) over 24 resident
+volumes (22 of the batched recipe and two 1024x1024x795 tube trees) served
+with continuous batching; p50/p99 latency and updates/s, beside the same
+schedule through a serial full-recompute queue (service times measured per
+volume on the GPU).
+
 --workload batched: 48 volumes of uneven sizes (96-640 per axis, half u8 and
 half 12-bit u16, 16/32/64 partitions).  Times the one-launch persistent build
 (launch shape from the autotuner) against a per-volume launch loop, and the
@@ -135,7 +141,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
-    ap.add_argument("--workload", default="tube_tree", choices=("tube_tree", "batched"))
+    ap.add_argument("--workload", default="tube_tree", choices=("tube_tree", "batched", "served"))
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -151,6 +159,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "served":
+        run_served(args)
         return
     cfg = W.config_info("c3")
     L, n = cfg["levels"], cfg["n"]
@@ -401,6 +412,96 @@ def run_batched(args):
                       "speedup_vs_loop": round(upd_loop_ms / upd_batch_ms, 3),
                       "GBps_batched": round(upd_bytes / (upd_batch_ms * 1e-3) / 1e9, 1),
                       "identical_to_loop": same_update},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serial_queue(schedule, service_s):
+    """Latencies of a single server taking requests in arrival order with the
+    given per-volume service times (seconds)."""
+    free = 0.0
+    lat = []
+    for r in schedule:
+        start = max(free, r.arrival)
+        free = start + service_s[r.vol_id]
+        lat.append(free - r.arrival)
+    lat = np.array(lat)
+    span = free - schedule[0].arrival
+    return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "updates_per_s": round(len(schedule) / span, 1)}
+
+
+def run_served(args):
+    import torch
+    import paper_2407_21552_amd as pdm
+    from paper_2407_21552_amd.serve import GpuExecutor, Server, VolumeSpec, requests_from
+    import workloads as W
+
+    log("generating the catalog (22 batch-recipe volumes + 2 tube trees) ...")
+    cat, host = {}, {}
+    for k, sp in enumerate(W.batch_specs(22, seed=6)):
+        host[k] = W.batch_volume(sp)
+        cat[k] = VolumeSpec(k, sp["shape"], sp["dtype"], sp["levels"],
+                            W.uniform_bounds(sp["levels"], sp["n"]), lambda k=k: host[k])
+    for j, seed in enumerate((3, 33)):
+        k = 22 + j
+        host[k] = W.tube_tree_u8(seed=seed)
+        cat[k] = VolumeSpec(k, host[k].shape, np.uint8, 256, W.uniform_bounds(256, 64),
+                            lambda k=k: host[k])
+    ex = GpuExecutor(outputs_per_volume=8)
+    srv = Server(ex, cat, budget_bytes=200 << 30, max_slots=24)
+    log("admitting all volumes (warm start) ...")
+    for k in cat:
+        srv._ensure(k)
+    torch.cuda.synchronize()
+    for h in srv.resident.values():
+        ex.ready(h)
+    sched = requests_from(W.poisson_requests(args.serve_rate, args.serve_seconds, list(cat),
+                                             {k: cat[k].levels for k in cat}, seed=12))
+    log(f"serving {len(sched)} requests over {args.serve_seconds:.0f} s ...")
+    srv.t0 = srv.clock()
+    srv.run(sched, timeout=args.serve_seconds + 60)
+    torch.cuda.synchronize()
+    rep = srv.report()
+
+    # per-volume service times of the plain method and of a single update
+    log("measuring per-volume full recompute and single update times ...")
+    stream = torch.cuda.current_stream()
+    full_s, upd_s = {}, {}
+    for k, h in srv.resident.items():
+        v = h.vol
+        vol_dev = pdm.to_device(host[k])
+        a = W.trapezoid_tf(cat[k].levels, 2, np.random.default_rng(k))
+        d = torch.empty_like(v.dist)
+        for name, fn, store in (("full", lambda: pdm.full_recompute(v.desc, vol_dev, a, d, stream), full_s),
+                                ("upd", lambda: pdm.tf_update(v.desc, v.pdms, v.bounds, a, d, stream), upd_s)):
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            store[k] = e0.elapsed_time(e1) / 5 * 1e-3
+        del vol_dev
+    out = {
+        "metric": "served TF updates: p50/p99 latency (ms) and updates/s, continuous batching",
+        "value": rep["updates_per_s"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic (22 batch-recipe volumes and two tube-tree volumes)",
+        "config": {"workload": f"Poisson {args.serve_rate:.0f}/s over {args.serve_seconds:.0f} s, "
+                               "24 resident volumes (22 U{96..640}^3 mixed u8/u16 + 2 x "
+                               "1024x1024x795 u8), 200 GB budget, up to 48 requests per launch",
+                   "requests": len(sched), "rate_hz": args.serve_rate},
+        "served": rep,
+        "serial_full_recompute": serial_queue(sched, full_s),
+        "serial_single_update": serial_queue(sched, upd_s),
+        "service_ms_mean": {"full_recompute": round(1e3 * float(np.mean(list(full_s.values()))), 4),
+                            "tf_update": round(1e3 * float(np.mean(list(upd_s.values()))), 4)},
     }
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,312 @@
+"""A TF-update server over resident partitioned distance maps.
+
+Requests are (volume id, opacity table).  The server keeps at most
+`max_slots` volumes resident within an HBM byte budget: a request for a
+non-resident volume admits it (upload + one-time PDM build on the admission
+stream), evicting the least recently used idle volumes until the new one fits.
+Serving is continuous batching: every tick gathers all queued requests whose
+volume is ready (up to `max_batch`) into ONE batched TF-update launch
+(pdm_batch_tf_update) on the update stream and returns at once; a tick does
+not wait for earlier ticks, so requests that arrive while others are on the
+GPU join the next launch and their work overlaps on the device with the
+running launches and with admissions.  A request completes when its launch's
+event has completed; latency is completion time minus arrival time.
+
+The scheduling logic is independent of the device: `Executor` is the
+interface, `GpuExecutor` runs the HIP library, and tests drive the same
+`Server` with a CPU executor to force admission, eviction and error paths.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class VolumeSpec:
+    """A volume the server can load: where its voxels come from and how it is
+    partitioned."""
+    vol_id: int
+    shape: tuple          # (nz, ny, nx)
+    dtype: object         # np.uint8 or np.uint16
+    levels: int
+    bounds: np.ndarray    # n+1 partition borders
+    load: Callable[[], np.ndarray]  # returns the voxels (host)
+
+    @property
+    def n(self) -> int:
+        return len(self.bounds) - 1
+
+    @property
+    def bricks(self) -> int:
+        nz, ny, nx = self.shape
+        return ((nz + 3) // 4) * ((ny + 3) // 4) * ((nx + 3) // 4)
+
+
+@dataclasses.dataclass
+class Request:
+    req_id: int
+    vol_id: int
+    alpha: np.ndarray
+    arrival: float                 # seconds on the server clock
+    done: Optional[float] = None   # completion time
+    result: object = None          # executor-specific output handle
+    error: Optional[str] = None
+
+
+class Executor:
+    """What the server needs from a device."""
+
+    def footprint(self, spec: VolumeSpec) -> int:
+        """Bytes a resident volume occupies (PDMs and outputs)."""
+        raise NotImplementedError
+
+    def admit(self, spec: VolumeSpec):
+        """Start making `spec` resident; returns a handle."""
+        raise NotImplementedError
+
+    def ready(self, handle) -> bool:
+        raise NotImplementedError
+
+    def evict(self, handle) -> None:
+        raise NotImplementedError
+
+    def launch(self, batch: List[tuple]):
+        """batch: list of (handle, alpha, request).  Start one batched update;
+        returns a ticket."""
+        raise NotImplementedError
+
+    def finished(self, ticket) -> bool:
+        raise NotImplementedError
+
+
+class Server:
+    def __init__(self, executor: Executor, catalog: Dict[int, VolumeSpec], budget_bytes: int,
+                 max_slots: int = 24, max_batch: int = 48, clock=time.perf_counter):
+        self.ex = executor
+        self.catalog = catalog
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.t0 = clock()
+        self.resident: "collections.OrderedDict[int, object]" = collections.OrderedDict()  # LRU order
+        self.used = 0
+        self.queue: List[Request] = []
+        self.inflight: List[tuple] = []   # (ticket, [requests])
+        self.busy: Dict[int, int] = collections.Counter()  # vol_id -> requests in flight
+        self.completed: List[Request] = []
+        self.rejected: List[Request] = []
+        self.stats = collections.Counter()
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    # ----------------------------------------------------------- residency
+    def _make_room(self, need: int) -> bool:
+        """Evict LRU idle volumes until `need` bytes and a slot are free."""
+        while (self.used + need > self.budget or len(self.resident) >= self.max_slots):
+            victim = next((v for v in self.resident if self.busy[v] == 0
+                           and not any(r.vol_id == v for r in self.queue)), None)
+            if victim is None:
+                victim = next((v for v in self.resident if self.busy[v] == 0), None)
+            if victim is None:
+                return False
+            self.ex.evict(self.resident.pop(victim))
+            self.used -= self.ex.footprint(self.catalog[victim])
+            self.stats["evictions"] += 1
+        return True
+
+    def _ensure(self, vol_id: int) -> Optional[object]:
+        if vol_id in self.resident:
+            self.resident.move_to_end(vol_id)
+            return self.resident[vol_id]
+        spec = self.catalog[vol_id]
+        need = self.ex.footprint(spec)
+        if need > self.budget:
+            return None
+        if not self._make_room(need):
+            return "wait"
+        h = self.ex.admit(spec)
+        self.resident[vol_id] = h
+        self.used += need
+        self.stats["admissions"] += 1
+        return h
+
+    # ------------------------------------------------------------- serving
+    def submit(self, req: Request) -> None:
+        spec = self.catalog.get(req.vol_id)
+        if spec is None:
+            req.error = "unknown volume"
+        elif np.asarray(req.alpha).shape != (spec.levels,):
+            req.error = "opacity table of the wrong length"
+        elif self.ex.footprint(spec) > self.budget:
+            req.error = "volume larger than the memory budget"
+        if req.error:
+            self.rejected.append(req)
+            return
+        self.queue.append(req)
+
+    def _retire(self) -> None:
+        still = []
+        for ticket, reqs in self.inflight:
+            if self.ex.finished(ticket):
+                t = self.now()
+                for r in reqs:
+                    r.done = t
+                    self.busy[r.vol_id] -= 1
+                    self.completed.append(r)
+            else:
+                still.append((ticket, reqs))
+        self.inflight = still
+
+    def tick(self) -> int:
+        """Retire finished launches, admit volumes for queued requests, and
+        launch one batch of ready requests.  Returns the batch size."""
+        self._retire()
+        batch, rest = [], []
+        for r in self.queue:
+            if len(batch) >= self.max_batch:
+                rest.append(r)
+                continue
+            h = self._ensure(r.vol_id)
+            if h is None:
+                r.error = "volume larger than the memory budget"
+                self.rejected.append(r)
+            elif isinstance(h, str) or not self.ex.ready(h):
+                rest.append(r)
+            else:
+                # counted busy at once, so a later admission in this tick
+                # cannot evict this volume
+                self.busy[r.vol_id] += 1
+                batch.append((h, r.alpha, r))
+        self.queue = rest
+        if batch:
+            self.inflight.append((self.ex.launch(batch), [r for _, _, r in batch]))
+            self.stats["launches"] += 1
+            self.stats["batched_requests"] += len(batch)
+        return len(batch)
+
+    def drain(self, timeout: float = 60.0) -> None:
+        end = self.now() + timeout
+        while (self.queue or self.inflight) and self.now() < end:
+            if self.tick() == 0:
+                time.sleep(0.0002)
+
+    def run(self, schedule: List[Request], timeout: float = 120.0) -> None:
+        """Feed requests at their arrival times (server clock) and serve
+        until all are done."""
+        schedule = sorted(schedule, key=lambda r: r.arrival)
+        i = 0
+        end = self.now() + timeout
+        while (i < len(schedule) or self.queue or self.inflight) and self.now() < end:
+            t = self.now()
+            while i < len(schedule) and schedule[i].arrival <= t:
+                self.submit(schedule[i])
+                i += 1
+            if self.tick() == 0:
+                time.sleep(0.0001)
+
+    def report(self) -> dict:
+        lat = np.array([r.done - r.arrival for r in self.completed]) if self.completed else np.zeros(0)
+        span = (max(r.done for r in self.completed) - min(r.arrival for r in self.completed)
+                if self.completed else 0.0)
+        return {
+            "completed": len(self.completed),
+            "rejected": len(self.rejected),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "mean_ms": float(lat.mean() * 1e3) if lat.size else None,
+            "updates_per_s": len(self.completed) / span if span > 0 else None,
+            "launches": self.stats["launches"],
+            "mean_batch": (self.stats["batched_requests"] / self.stats["launches"]
+                           if self.stats["launches"] else None),
+            "admissions": self.stats["admissions"],
+            "evictions": self.stats["evictions"],
+        }
+
+
+def requests_from(arrivals) -> List[Request]:
+    """Requests from (arrival seconds, volume id, opacity table) tuples."""
+    return [Request(k, int(v), np.asarray(alpha, np.float32), float(t))
+            for k, (t, v, alpha) in enumerate(arrivals)]
+
+
+class GpuExecutor(Executor):
+    """Runs the server on the GPU through the C ABI.  Admission uploads the
+    voxels and builds bricks and PDMs on `admit_stream`; updates run on
+    `update_stream`, one batched launch per tick; each request gets its own
+    output map from a per-volume pool of `outputs_per_volume` buffers."""
+
+    def __init__(self, outputs_per_volume: int = 8, keep_volume: bool = False):
+        import torch
+        self.torch = torch
+        self.admit_stream = torch.cuda.Stream()
+        self.update_stream = torch.cuda.Stream()
+        self.outputs = int(outputs_per_volume)
+        self.keep_volume = keep_volume
+
+    def footprint(self, spec: VolumeSpec) -> int:
+        G = spec.bricks
+        s = np.dtype(spec.dtype).itemsize
+        vox = int(np.prod(spec.shape)) * s
+        return spec.n * G + self.outputs * G + 2 * G * s + (vox if self.keep_volume else 0)
+
+    class Handle:
+        pass
+
+    def admit(self, spec: VolumeSpec):
+        import paper_2407_21552_amd as pdm
+        torch = self.torch
+        h = GpuExecutor.Handle()
+        h.spec = spec
+        vox = spec.load()
+        with torch.cuda.stream(self.admit_stream):
+            h.vol = pdm.Volume(pdm.to_device(vox), spec.levels, spec.bounds, voxel_dtype=spec.dtype)
+            h.vol.build(self.admit_stream)
+            h.outs = [torch.empty_like(h.vol.dist) for _ in range(self.outputs)]
+            h.next_out = 0
+            h.ready_ev = torch.cuda.Event()
+            h.ready_ev.record(self.admit_stream)
+        # PDMs and outputs are used on the update stream: keep the allocator
+        # from reusing them while launches there may still run
+        h.vol.pdms.record_stream(self.update_stream)
+        for o in h.outs:
+            o.record_stream(self.update_stream)
+        # the server launches a volume's requests only once ready() has seen
+        # the build event complete, so the update stream needs no wait here
+        # (a wait would hold every later tick behind this build)
+        h.drop_volume_after_ready = not self.keep_volume
+        return h
+
+    def ready(self, h) -> bool:
+        ok = h.ready_ev.query()
+        if ok and getattr(h, "drop_volume_after_ready", False):
+            h.vol.volume = None  # voxels are not needed once the PDMs exist
+            h.drop_volume_after_ready = False
+        return ok
+
+    def evict(self, h) -> None:
+        h.vol = None
+        h.outs = None
+
+    def launch(self, batch):
+        import paper_2407_21552_amd as pdm
+        torch = self.torch
+        items = []
+        for h, alpha, req in batch:
+            out = h.outs[h.next_out]
+            h.next_out = (h.next_out + 1) % len(h.outs)
+            req.result = out
+            items.append((h.vol.desc, h.vol.pdms, h.vol.bounds, alpha, out))
+        pdm.batch_tf_update(items, self.update_stream)
+        ev = torch.cuda.Event()
+        ev.record(self.update_stream)
+        return ev
+
+    def finished(self, ev) -> bool:
+        return ev.query()

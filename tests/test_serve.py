@@ -1,0 +1,159 @@
+"""The TF-update server's scheduling on the CPU, with an executor that
+computes through the oracle: admission by memory budget and slot cap, LRU
+eviction of idle volumes, rejection of bad requests, continuous batching of
+requests that arrive while launches are in flight, and exact results."""
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2407_21552_amd.serve import Executor, Request, Server, VolumeSpec, requests_from
+
+
+class OracleExecutor(Executor):
+    """Synchronous CPU executor; a launch 'finishes' after `delay` ticks."""
+
+    def __init__(self, orc, delay=0):
+        self.orc = orc
+        self.delay = delay
+        self.events = []
+        self.launches = []
+
+    def footprint(self, spec):
+        return spec.n * spec.bricks + 2 * spec.bricks
+
+    def admit(self, spec):
+        vol = spec.load()
+        h = dict(spec=spec, pdms=self.orc.pdms(vol, spec.bounds, spec.levels), alive=True)
+        self.events.append(("admit", spec.vol_id))
+        return h
+
+    def ready(self, h):
+        return True
+
+    def evict(self, h):
+        h["alive"] = False
+        self.events.append(("evict", h["spec"].vol_id))
+
+    def launch(self, batch):
+        for h, alpha, req in batch:
+            assert h["alive"]
+            req.result = self.orc.tf_update(h["pdms"], h["spec"].bounds, alpha, h["spec"].levels)[0]
+        self.launches.append([req.req_id for _, _, req in batch])
+        return [self.delay]
+
+    def finished(self, ticket):
+        if ticket[0] <= 0:
+            return True
+        ticket[0] -= 1
+        return False
+
+
+def catalog(k=5, seed=0):
+    rng = np.random.default_rng(seed)
+    out = {}
+    for v in range(k):
+        shape = tuple(int(s) for s in rng.integers(8, 24, size=3))
+        vol = rng.integers(0, 256, size=shape).astype(np.uint8)
+        vol[rng.random(shape) < 0.8] = 0
+        out[v] = VolumeSpec(v, shape, np.uint8, 256, W.uniform_bounds(256, 8), lambda vol=vol: vol)
+    return out
+
+
+def tfs(rng, k):
+    return [W.trapezoid_tf(256, int(rng.integers(1, 4)), rng) for _ in range(k)]
+
+
+def test_results_are_exact(orc):
+    cat = catalog()
+    ex = OracleExecutor(orc)
+    srv = Server(ex, cat, budget_bytes=10**9)
+    rng = np.random.default_rng(1)
+    reqs = [Request(i, int(rng.integers(0, 5)), a, 0.0) for i, a in enumerate(tfs(rng, 30))]
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    assert len(srv.completed) == 30 and not srv.rejected
+    for r in reqs:
+        spec = cat[r.vol_id]
+        want = orc.tf_update(orc.pdms(spec.load(), spec.bounds, 256), spec.bounds, r.alpha, 256)[0]
+        np.testing.assert_array_equal(r.result, want)
+
+
+def test_slot_cap_and_lru_eviction(orc):
+    cat = catalog(6)
+    ex = OracleExecutor(orc)
+    srv = Server(ex, cat, budget_bytes=10**9, max_slots=3)
+    rng = np.random.default_rng(2)
+    order = [0, 1, 2, 0, 3, 4, 0, 5]
+    for i, v in enumerate(order):
+        srv.submit(Request(i, v, tfs(rng, 1)[0], 0.0))
+        srv.drain()
+    assert len(srv.resident) <= 3
+    # 0 is used again before 3 arrives, so 1 (least recently used) goes first
+    evicted = [v for kind, v in ex.events if kind == "evict"]
+    assert evicted[0] == 1
+    assert 0 in srv.resident
+    assert len(srv.completed) == len(order)
+
+
+def test_memory_budget_forces_eviction(orc):
+    cat = catalog(4)
+    ex = OracleExecutor(orc)
+    largest = max(ex.footprint(s) for s in cat.values())
+    srv = Server(ex, cat, budget_bytes=largest + 1, max_slots=24)
+    rng = np.random.default_rng(3)
+    for i, v in enumerate([0, 1, 2, 3, 0]):
+        srv.submit(Request(i, v, tfs(rng, 1)[0], 0.0))
+        srv.drain()
+        assert srv.used <= srv.budget
+    assert srv.stats["evictions"] >= 3
+    assert len(srv.completed) == 5
+
+
+def test_bad_requests_are_rejected(orc):
+    cat = catalog(2)
+    ex = OracleExecutor(orc)
+    srv = Server(ex, cat, budget_bytes=10**9)
+    srv.submit(Request(0, 99, np.zeros(256, np.float32), 0.0))       # unknown volume
+    srv.submit(Request(1, 0, np.zeros(100, np.float32), 0.0))        # wrong table length
+    tiny = Server(ex, cat, budget_bytes=10)
+    tiny.submit(Request(2, 1, np.zeros(256, np.float32), 0.0))        # larger than the budget
+    srv.drain()
+    tiny.drain()
+    assert [r.req_id for r in srv.rejected] == [0, 1]
+    assert [r.req_id for r in tiny.rejected] == [2]
+    assert all(r.error for r in srv.rejected + tiny.rejected)
+
+
+def test_requests_arriving_during_a_launch_join_the_next_one(orc):
+    cat = catalog(3)
+    ex = OracleExecutor(orc, delay=3)
+    srv = Server(ex, cat, budget_bytes=10**9)
+    rng = np.random.default_rng(4)
+    a = tfs(rng, 6)
+    for i in range(2):
+        srv.submit(Request(i, i % 3, a[i], 0.0))
+    assert srv.tick() == 2                       # first launch, still in flight
+    for i in range(2, 6):
+        srv.submit(Request(i, i % 3, a[i], 0.0))
+    assert srv.tick() == 4                       # admitted while the first runs
+    assert len(srv.inflight) == 2
+    srv.drain()
+    assert ex.launches == [[0, 1], [2, 3, 4, 5]]
+    assert len(srv.completed) == 6
+
+
+def test_max_batch_and_poisson_schedule(orc):
+    cat = catalog(3)
+    ex = OracleExecutor(orc)
+    srv = Server(ex, cat, budget_bytes=10**9, max_batch=4)
+    sched = requests_from(W.poisson_requests(2000.0, 0.01, list(cat), {v: 256 for v in cat}, seed=9))
+    assert 5 <= len(sched) <= 60
+    assert all(b.arrival >= a.arrival for a, b in zip(sched, sched[1:]))
+    for r in sched:
+        srv.submit(r)
+    srv.drain()
+    assert all(len(b) <= 4 for b in ex.launches)
+    assert len(srv.completed) == len(sched)
+    rep = srv.report()
+    assert rep["completed"] == len(sched) and rep["p99_ms"] >= rep["p50_ms"]

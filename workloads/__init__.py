@@ -37,7 +37,7 @@ def _chunk_map(fn, nz: int, seed: int, salt: int):
 __all__ = [
     "CONFIGS", "ellipsoids_u8", "ct_like_u16", "tube_tree_u8", "make_volume",
     "trapezoid_tf", "make_tfs", "uniform_bounds", "rhomin_bounds", "config_info",
-    "batch_specs", "batch_volume",
+    "batch_specs", "batch_volume", "poisson_requests",
 ]
 
 # name -> (shape (nz,ny,nx), dtype, levels L, partitions n, volume seed,
@@ -294,6 +294,24 @@ def make_tfs(name: str, count=None):
         rng = np.random.default_rng(c["tf_seed"] + k)
         r = int(rng.integers(c["ramps"][0], c["ramps"][1] + 1))
         out.append(trapezoid_tf(c["levels"], r, rng))
+    return out
+
+
+def poisson_requests(rate_hz: float, seconds: float, vol_ids, levels_of, ramps=(1, 4), seed: int = 5):
+    """A Poisson stream of TF-change requests: exponential inter-arrival gaps
+    of mean 1/rate_hz over [0, seconds), each with a uniformly random volume id
+    and a random trapezoid TF of U{ramps} ramps.  Returns a list of
+    (arrival seconds, volume id, opacity table)."""
+    rng = np.random.default_rng(seed)
+    vol_ids = list(vol_ids)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= seconds:
+            break
+        v = vol_ids[int(rng.integers(0, len(vol_ids)))]
+        alpha = trapezoid_tf(levels_of[v], int(rng.integers(ramps[0], ramps[1] + 1)), rng)
+        out.append((t, v, alpha))
     return out
 
 
