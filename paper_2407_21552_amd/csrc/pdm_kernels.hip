@@ -915,30 +915,54 @@ __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
 // wave exits.  Completion: the wave's stores are released at agent scope
 // before its counter increment; waiters acquire at agent scope (the L2s of
 // the XCDs are not coherent with each other).  One wave per work-group.
+//
+// Every value that steers control flow (ticket, phase, volume, counter
+// reads, wait outcome) is made wave-uniform with readfirstlane, and lane-0
+// atomics sit in plain if-blocks that rejoin at once.  A value broadcast by
+// a shuffle looks divergent to the compiler, which may then restructure the
+// loop so that lane 0's completion increment runs only after the other
+// lanes leave the loop: the counter then never moves while they wait.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool wait_done(const uint32_t* cnt, uint32_t target, uint32_t* err,
-                                          uint32_t spin_limit) {
-    uint32_t ok = 1;
-    if (threadIdx.x == 0) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > spin_limit ||
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(4);
-        }
-        if (!ok) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    ok = (uint32_t)__shfl((int)ok, 0, kWave);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok != 0u;
+// Counters are read and written only with value-returning atomics, the
+// form the ticket counter uses: a plain load, even at agent scope, may be
+// served from an XCD's own L2 and never observe increments made elsewhere.
+__device__ __forceinline__ uint32_t lane0_fetch_add(uint32_t* cnt, uint32_t add) {
+    uint32_t r = 0;
+    if (threadIdx.x == 0)
+        r = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(r);
 }
 
-__device__ __forceinline__ void mark_done(uint32_t* cnt) {
+__device__ __forceinline__ uint32_t counter_read(uint32_t* cnt) {
+    // an addend the compiler cannot see is zero: an add of a known zero is
+    // rewritten into a plain load
+    uint32_t zero;
+    __asm__ volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return lane0_fetch_add(cnt, zero);
+}
+
+__device__ __forceinline__ bool wait_done(uint32_t* cnt, uint32_t target, uint32_t* err,
+                                          uint32_t spin_limit) {
+    bool ok = true;
+    for (uint32_t spins = 0; counter_read(cnt) < target; ++spins) {
+        if (spins >= spin_limit || counter_read(err) != 0u) {
+            ok = false;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    if (!ok && threadIdx.x == 0) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+__device__ __forceinline__ void mark_done(uint32_t* cnt, uint32_t* err) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t before = lane0_fetch_add(cnt, 1u);
+    // a counter never reaches 2^32 - 1 items; the test keeps the
+    // value-returning form of the atomic
+    if (before == 0xFFFFFFFFu && threadIdx.x == 0)
+        __hip_atomic_fetch_or(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Phase 0 for one z slice of one volume (Bx <= 256: one segment per row).
@@ -981,12 +1005,9 @@ __global__ void __launch_bounds__(kWave) k_batch_build(const BatchVol* __restric
     __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
     const int lane = threadIdx.x;
     for (;;) {
-        int64_t t = 0;
-        if (lane == 0) t = (int64_t)__hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-        t = (int64_t)__shfl((int)t, 0, kWave);
+        const int64_t t = (int64_t)lane0_fetch_add(&st->ticket, 1u);
         if (t >= total) break;
-        if (__hip_atomic_load(&st->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        if (counter_read(&st->error) != 0u) break;
         // locate (phase, volume) of ticket t
         int ph = 2;
         while (ph > 0 && t < vols[0].first[ph]) --ph;
@@ -999,7 +1020,7 @@ __global__ void __launch_bounds__(kWave) k_batch_build(const BatchVol* __restric
                 batch_rows<uint8_t>(d, (int)local);
             else
                 batch_rows<uint16_t>(d, (int)local);
-            mark_done(&st->done[0][v]);
+            mark_done(&st->done[0][v], &st->error);
             continue;
         }
         if (!wait_done(&st->done[ph - 1][v], (uint32_t)d.items[ph - 1], &st->error, spin_limit)) break;
@@ -1032,7 +1053,7 @@ __global__ void __launch_bounds__(kWave) k_batch_build(const BatchVol* __restric
                 one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
             }
         }
-        mark_done(&st->done[ph][v]);
+        mark_done(&st->done[ph][v], &st->error);
     }
 }
 
