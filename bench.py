@@ -368,7 +368,6 @@ def run_batched(args):
     for v in vols:
         v.pdms.fill_(0)
     batch_ms = timed(lambda: pdm.batch_build(items, ws, best, stream), args.steps)
-    assert pdm.batch_error(ws) == 0, "batched build failed"
     same_build = all(bool(torch.equal(a, v.pdms)) for a, v in zip(ref, vols))
     default_ms = timed(lambda: pdm.batch_build(items, ws, None, stream), args.steps)
 
@@ -379,11 +378,11 @@ def run_batched(args):
         for v, a, o in zip(vols, alphas, outs_loop):
             pdm.tf_update(v.desc, v.pdms, v.bounds, a, o, stream)
 
-    upd_items = [(v.desc, v.pdms, v.bounds, a, o) for v, a, o in zip(vols, alphas, outs_batch)]
+    upd_items = [(v.prepared, a, o) for v, a, o in zip(vols, alphas, outs_batch)]
     log("TF updates: per-volume loop vs one launch ...")
     upd_loop_ms = timed(loop_update, 20)
-    masks = pdm.batch_tf_update(upd_items, stream)
-    upd_batch_ms = timed(lambda: pdm.batch_tf_update(upd_items, stream), 20)
+    masks = pdm.batch_tf_update_prepared(upd_items, stream)
+    upd_batch_ms = timed(lambda: pdm.batch_tf_update_prepared(upd_items, stream), 20)
     same_update = all(bool(torch.equal(a, b)) for a, b in zip(outs_loop, outs_batch))
 
     G_tot = sum(v.G for v in vols)

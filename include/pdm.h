@@ -151,18 +151,18 @@ pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
                                uint64_t* h_active, hipStream_t stream);
 
 /* Batched one-time initialisation: pdm_build_bricks + pdm_build_partitions
- * for up to PDM_BATCH_MAX volumes of different sizes, dtypes and partition
- * counts in ONE persistent kernel launch fed from a device work queue
- * (bricks and x distances per z slice, then y passes, then z passes; each
- * volume's next phase starts when its previous phase is done).  Results are
- * identical to the single-volume calls.  Every grid axis must be <= 256
- * bricks (else PDM_E_UNSUPPORTED).
+ * (Sec. 3.1: brick [min,max], then every partition's POM and its distance
+ * transform) for up to PDM_BATCH_MAX volumes of different sizes, dtypes and
+ * partition counts in three grouped launches, each covering every volume:
+ * bricks + POM x distances per group of brick rows, then all y passes, then
+ * all z passes.  Results are identical to the single-volume calls.  Every
+ * grid axis must be <= 256 bricks (else PDM_E_UNSUPPORTED).  Voxel values are
+ * not range-checked here (pdm_build_bricks reports them).
  *
  * d_workspace: device memory of pdm_batch_workspace_bytes(count) bytes,
- * 16-byte aligned, owned by the caller, not used by any other call until the
- * build is done.  Its first 8 bytes are two uint32 words {next ticket,
- * error}: after the stream completes, error != 0 means a work item gave up
- * waiting (never expected; the outputs are then incomplete).
+ * 16-byte aligned, owned by the caller; it receives the volume descriptors
+ * and must not be used by another call until the stream has passed this
+ * build.
  * cfg: nullable tuning knobs (see pdm_batch_config); results do not depend on
  * them. */
 typedef struct {
@@ -176,9 +176,9 @@ typedef struct {
 } pdm_batch_volume;
 
 typedef struct {
-    int32_t waves;          /* resident one-wave work-groups; 0 = 8 per compute unit */
+    int32_t rows_per_item;  /* brick rows per first-phase work item, 1..256; 0 = 4 */
     int32_t lines_mult;     /* 64-line groups per y/z work item, 1..16; 0 = 1 */
-    int32_t largest_first;  /* 1: hand out the largest volumes' items first */
+    int32_t largest_first;  /* 1: order the volumes' items by decreasing work */
     int32_t reserved;
 } pdm_batch_config;
 

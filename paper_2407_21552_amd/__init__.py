@@ -16,16 +16,17 @@ from __future__ import annotations
 import numpy as np
 
 from . import _lib
-from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, active_set,
-                   batch_build, batch_error, batch_tf_update, batch_workspace_bytes, build_bricks,
+from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, PreparedVolume,
+                   active_set, batch_build, batch_tf_update, batch_tf_update_prepared,
+                   batch_workspace_bytes, build_bricks,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
                    full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
                    volume_desc)
 
-__all__ = ["Volume", "PdmError", "active_set", "batch_build", "batch_error", "batch_tf_update",
-           "batch_workspace_bytes", "BATCH_MAX", "build_bricks",
-           "build_partitions",
+__all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build",
+           "batch_tf_update", "batch_tf_update_prepared", "batch_workspace_bytes", "BATCH_MAX",
+           "build_bricks", "build_partitions",
            "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
            "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
            "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",
@@ -93,6 +94,13 @@ class Volume:
             build_partitions_exact(self.desc, self.volume, self.bounds, self.pdms, stream)
         else:
             build_partitions(self.desc, self.bmin, self.bmax, self.bounds, self.pdms, stream)
+
+    @property
+    def prepared(self) -> PreparedVolume:
+        """This volume's fixed batched-update fields (built once)."""
+        if getattr(self, "_prepared", None) is None:
+            self._prepared = PreparedVolume(self.desc, self.pdms, self.bounds)
+        return self._prepared
 
     def check_range(self) -> None:
         """Synchronises; raises PdmError if some voxel was >= levels."""

@@ -53,7 +53,7 @@ class BatchVolume(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("waves", ctypes.c_int32), ("lines_mult", ctypes.c_int32),
+    _fields_ = [("rows_per_item", ctypes.c_int32), ("lines_mult", ctypes.c_int32),
                 ("largest_first", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -339,16 +339,73 @@ def batch_tf_update(items, stream=None) -> np.ndarray:
     return masks
 
 
+_BATCH_UPDATE_DTYPE = np.dtype({
+    "names": ["v", "d_pdms", "h_bounds", "n", "h_alpha", "d_dist"],
+    "formats": [np.uint64, np.uint64, np.uint64, np.int32, np.uint64, np.uint64],
+    "offsets": [BatchUpdate.v.offset, BatchUpdate.d_pdms.offset, BatchUpdate.h_bounds.offset,
+                BatchUpdate.n.offset, BatchUpdate.h_alpha.offset, BatchUpdate.d_dist.offset],
+    "itemsize": ctypes.sizeof(BatchUpdate)})
+
+
+class PreparedVolume:
+    """The fixed part of a resident volume's batched-update item (descriptor,
+    PDMs, partition borders), checked once so that a launch only adds the
+    opacity tables and output maps.  The PDM tensor must stay alive and
+    unchanged in place while the object is used."""
+    __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed")
+
+    def __init__(self, desc, pdms, bounds):
+        self.desc = desc
+        self.levels = int(desc.levels)
+        self.G = grid_of(desc)[3]
+        self.bounds = _bounds(bounds)
+        self.n = len(self.bounds) - 1
+        if not 1 <= self.n <= 256:
+            raise ValueError(f"1..256 partitions, got {self.n}")
+        _dev_ptr(pdms, self.n * self.G, "pdms")
+        self.pdms = pdms
+        self.fixed = (ctypes.addressof(desc), pdms.data_ptr(), self.bounds.ctypes.data, self.n)
+
+
+def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
+    """batch_tf_update over prepared volumes.  entries: sequence of
+    (PreparedVolume, alpha, dist): alpha holds the volume's `levels` opacities
+    (float32), dist is a contiguous device tensor of G bytes.  Returns the S
+    masks, shape (count, 4)."""
+    count = len(entries)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
+    arr = np.empty(count, _BATCH_UPDATE_DTYPE)
+    keep = []
+    for k, (pv, alpha, dist) in enumerate(entries):
+        a = alpha
+        if not (type(a) is np.ndarray and a.dtype == np.float32 and a.flags.c_contiguous):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        if a.shape != (pv.levels,):
+            raise ValueError(f"alpha {k} must hold {pv.levels} float32 entries, got shape {a.shape}")
+        if not dist.is_cuda or not dist.is_contiguous() or dist.numel() * dist.element_size() != pv.G:
+            raise ValueError(f"dist {k}: expected a contiguous device tensor of {pv.G} bytes")
+        keep.append(a)
+        v, pd, b, n = pv.fixed
+        arr[k] = (v, pd, b, n, a.ctypes.data, dist.data_ptr())
+    masks = np.zeros((count, 4), np.uint64)
+    _check(lib().pdm_batch_tf_update(arr.ctypes.data_as(ctypes.POINTER(BatchUpdate)), count,
+                                     _np_ptr(masks), _stream(stream)), "pdm_batch_tf_update")
+    del keep
+    return masks
+
+
 # ------------------------------------------------------------- batched build
 def batch_workspace_bytes(count: int) -> int:
     return int(lib().pdm_batch_workspace_bytes(int(count)))
 
 
 def batch_build(items, workspace, config=None, stream=None) -> None:
-    """One persistent launch building bricks and PDMs of several volumes.
+    """Bricks and PDMs of several volumes in three grouped launches.
     items: sequence of (desc, volume, bmin, bmax, bounds, pdms); workspace: a
-    uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more;
-    config: None or dict(waves=, lines_mult=, largest_first=)."""
+    uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more
+    (it receives the descriptors; keep it until the stream has passed);
+    config: None or dict(rows_per_item=, lines_mult=, largest_first=)."""
     count = len(items)
     if not 1 <= count <= BATCH_MAX:
         raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
@@ -372,15 +429,10 @@ def batch_build(items, workspace, config=None, stream=None) -> None:
         raise ValueError(f"workspace holds {ws_bytes} bytes, needs {need}")
     cfg = None
     if config is not None:
-        cfg = ctypes.pointer(BatchConfig(int(config.get("waves", 0)),
+        cfg = ctypes.pointer(BatchConfig(int(config.get("rows_per_item", 0)),
                                          int(config.get("lines_mult", 0)),
                                          int(config.get("largest_first", 0)), 0))
     _check(lib().pdm_batch_build(arr, count, _dev_ptr(workspace, ws_bytes, "workspace"),
                                  ws_bytes, cfg, _stream(stream)), "pdm_batch_build")
     del keep
 
-
-def batch_error(workspace) -> int:
-    """The error word of a batch-build workspace (synchronises)."""
-    import torch
-    return int(workspace[4:8].view(torch.int32).item())

@@ -231,7 +231,7 @@ pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
 
 size_t pdm_batch_workspace_bytes(int32_t count) {
     if (count < 1 || count > PDM_BATCH_MAX) return 0;
-    return sizeof(pdm::BatchState) + 16 + (size_t)count * sizeof(pdm::BatchVol);
+    return (size_t)count * sizeof(pdm::BatchVol);
 }
 
 pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
@@ -241,12 +241,12 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
     if (d_workspace == nullptr || !aligned(d_workspace, 16) ||
         workspace_bytes < pdm_batch_workspace_bytes(count))
         return PDM_E_INVAL;
-    pdm_batch_config c = {0, 1, 0, 0};
+    pdm_batch_config c = {0, 0, 0, 0};
     if (cfg != nullptr) c = *cfg;
-    if (c.waves < 0 || c.lines_mult < 0 || c.lines_mult > 16) return PDM_E_INVAL;
+    if (c.rows_per_item < 0 || c.rows_per_item > 256 || c.lines_mult < 0 || c.lines_mult > 16)
+        return PDM_E_INVAL;
     if (c.lines_mult == 0) c.lines_mult = 1;
-    if (c.waves == 0) c.waves = 8 * 256;
-    static_assert(PDM_BATCH_MAX <= PDM_BATCH_MAX_ITEMS, "batch descriptors exceed the state");
+    if (c.rows_per_item == 0) c.rows_per_item = 4;
     // host staging of the descriptors (copied to the workspace by the launcher)
     pdm::BatchVol tmp[PDM_BATCH_MAX];
     pdm::BatchVol vols[PDM_BATCH_MAX];
@@ -283,12 +283,14 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         for (int32_t p = 0; p <= it.n; ++p) d.bounds[p] = it.h_bounds[p];
         const int64_t lines = (int64_t)it.n * g.bx;
         d.chunks = (int32_t)((lines + 64 * c.lines_mult - 1) / (64 * c.lines_mult));
-        d.items[0] = g.bz;
-        d.items[1] = g.bz * d.chunks;
-        d.items[2] = g.by * d.chunks;
+        d.rows = c.rows_per_item;
+        d.row_groups = (g.by + c.rows_per_item - 1) / c.rows_per_item;
+        d.items[0] = g.bz * d.row_groups;
+        d.items[1] = g.by > 1 ? g.bz * d.chunks : 0;  // a pass over lines of 1 brick is the identity
+        d.items[2] = g.bz > 1 ? g.by * d.chunks : 0;
         work[k] = (int64_t)it.n * g.count;
     }
-    // hand-out order of the volumes (the same in every phase)
+    // order of the volumes' items (the same in every phase)
     int32_t order[PDM_BATCH_MAX];
     for (int32_t k = 0; k < count; ++k) order[k] = k;
     if (c.largest_first)
@@ -299,18 +301,16 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
                 order[b - 1] = t;
             }
     for (int32_t k = 0; k < count; ++k) vols[k] = tmp[order[k]];
-    int64_t t = 0;
+    int64_t totals[3] = {0, 0, 0};
     for (int ph = 0; ph < 3; ++ph)
         for (int32_t k = 0; k < count; ++k) {
-            vols[k].first[ph] = t;
-            t += vols[k].items[ph];
+            vols[k].first[ph] = totals[ph];
+            totals[ph] += vols[k].items[ph];
         }
-    if (t > INT32_MAX) return PDM_E_UNSUPPORTED;
-    uint8_t* ws = static_cast<uint8_t*>(d_workspace);
-    pdm::BatchState* state = reinterpret_cast<pdm::BatchState*>(ws);
-    pdm::BatchVol* dv = reinterpret_cast<pdm::BatchVol*>(ws + ((sizeof(pdm::BatchState) + 15) & ~(size_t)15));
-    return from_hip(pdm::launch_batch_build(vols, count, dv, state, t, c.waves, 1u << 24,
-                                            c.lines_mult, stream));
+    for (int ph = 0; ph < 3; ++ph)
+        if (totals[ph] > INT32_MAX - 64) return PDM_E_UNSUPPORTED;
+    pdm::BatchVol* dv = static_cast<pdm::BatchVol*>(d_workspace);
+    return from_hip(pdm::launch_batch_build(vols, count, dv, totals, c.lines_mult, stream));
 }
 
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,

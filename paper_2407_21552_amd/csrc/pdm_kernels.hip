@@ -899,81 +899,55 @@ __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_batch_build: the one-time initialisation of many volumes in one
-// persistent launch.  Work items are handed out in order from a device
-// ticket counter:
-//   phase 0  (volume, z slice): brick [min,max] of every row of the slice,
-//            then every partition's POM row and x distances (bricks + POM x
-//            fused: the volume is read once);
-//   phase 1  (volume, z slice, 64-line chunk): y pass of lines (p, z, x);
-//   phase 2  (volume, y row, 64-line chunk): z pass of lines (p, y, x).
-// All phase-0 tickets come before all phase-1 tickets and those before all
-// phase-2 tickets.  A phase-1 (2) item of volume v waits until every phase-0
-// (1) item of v is done; those hold smaller tickets, taken earlier by running
-// work-groups, so the wait always ends.  Each wait is still bounded: after
-// spin_limit polls the work-group sets the error flag and stops, so every
-// wave exits.  Completion: the wave's stores are released at agent scope
-// before its counter increment; waiters acquire at agent scope (the L2s of
-// the XCDs are not coherent with each other).  One wave per work-group.
-//
-// Every value that steers control flow (ticket, phase, volume, counter
-// reads, wait outcome) is made wave-uniform with readfirstlane, and lane-0
-// atomics sit in plain if-blocks that rejoin at once.  A value broadcast by
-// a shuffle looks divergent to the compiler, which may then restructure the
-// loop so that lane 0's completion increment runs only after the other
-// lanes leave the loop: the counter then never moves while they wait.
+// Batched build: the one-time initialisation of many volumes in three
+// grouped launches, each covering every volume of the batch:
+//   rows  item (volume, z slice, group of brick rows): brick [min,max] of the
+//         rows, then every partition's POM row and x distances (bricks and
+//         POM x fused: the volume is read once);
+//   y     item (volume, z slice, chunk of 64*lines_mult lines (p, x));
+//   z     item (volume, y row, chunk of 64*lines_mult lines (p, x)).
+// Launch boundaries order the phases, so no work-group waits on another.
+// The items of a phase are numbered volume by volume in descriptor order
+// (first[ph] is the running prefix).  Work-groups are handed to the XCDs
+// round-robin; xcd_item maps them so that runs of kXcdRun consecutive items
+// land on one XCD, keeping neighbouring chunks, which share cache lines,
+// under one L2.
 // ---------------------------------------------------------------------------
-// Counters are read and written only with value-returning atomics, the
-// form the ticket counter uses: a plain load, even at agent scope, may be
-// served from an XCD's own L2 and never observe increments made elsewhere.
-__device__ __forceinline__ uint32_t lane0_fetch_add(uint32_t* cnt, uint32_t add) {
-    uint32_t r = 0;
-    if (threadIdx.x == 0)
-        r = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_amdgcn_readfirstlane(r);
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 4;
+
+__device__ __forceinline__ int64_t xcd_item(int64_t b) {
+    constexpr int64_t span = (int64_t)kXcds * kXcdRun;
+    const int64_t r = b % span;
+    return (b - r) + (r % kXcds) * kXcdRun + r / kXcds;
 }
 
-__device__ __forceinline__ uint32_t counter_read(uint32_t* cnt) {
-    // an addend the compiler cannot see is zero: an add of a known zero is
-    // rewritten into a plain load
-    uint32_t zero;
-    __asm__ volatile("v_mov_b32 %0, 0" : "=v"(zero));
-    return lane0_fetch_add(cnt, zero);
-}
-
-__device__ __forceinline__ bool wait_done(uint32_t* cnt, uint32_t target, uint32_t* err,
-                                          uint32_t spin_limit) {
-    bool ok = true;
-    for (uint32_t spins = 0; counter_read(cnt) < target; ++spins) {
-        if (spins >= spin_limit || counter_read(err) != 0u) {
-            ok = false;
-            break;
-        }
-        __builtin_amdgcn_s_sleep(4);
+// The volume holding item t of phase ph: the last descriptor whose first
+// item is <= t (volumes with no items in the phase share the next one's
+// first and are skipped by taking the last).
+__device__ __forceinline__ int batch_volume_of(const BatchVol* __restrict__ vols, int count, int ph,
+                                               int64_t t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vols[mid].first[ph] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    if (!ok && threadIdx.x == 0) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok;
+    return lo;
 }
 
-__device__ __forceinline__ void mark_done(uint32_t* cnt, uint32_t* err) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t before = lane0_fetch_add(cnt, 1u);
-    // a counter never reaches 2^32 - 1 items; the test keeps the
-    // value-returning form of the atomic
-    if (before == 0xFFFFFFFFu && threadIdx.x == 0)
-        __hip_atomic_fetch_or(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Phase 0 for one z slice of one volume (Bx <= 256: one segment per row).
+// First phase for brick rows [by0, by1) of z slice bz (Bx <= 256: one
+// segment per row).
 template <typename T>
-__device__ __forceinline__ void batch_rows(const BatchVol& d, int bz) {
+__device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, int by1) {
     const int lane = threadIdx.x;
     const T* vol = reinterpret_cast<const T*>(d.vol);
     T* bmin = reinterpret_cast<T*>(d.bmin);
     T* bmax = reinterpret_cast<T*>(d.bmax);
     const int nb = max(0, min(4, d.Bx - 4 * lane));
-    for (int by = 0; by < d.By; ++by) {
+    for (int by = by0; by < by1; ++by) {
         const int64_t rbase = ((int64_t)bz * d.By + by) * d.Bx;
         uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         uint32_t mx[4] = {0u, 0u, 0u, 0u};
@@ -999,66 +973,63 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz) {
     }
 }
 
-__global__ void __launch_bounds__(kWave) k_batch_build(const BatchVol* __restrict__ vols, int count,
-                                                       BatchState* __restrict__ st, int64_t total,
-                                                       uint32_t spin_limit, int lines_mult) {
+__global__ void __launch_bounds__(kWave) k_batch_rows(const BatchVol* __restrict__ vols, int count,
+                                                      int64_t total) {
+    const int64_t t = xcd_item(blockIdx.x);
+    if (t >= total) return;
+    const BatchVol& d = vols[batch_volume_of(vols, count, 0, t)];
+    const int64_t local = t - d.first[0];
+    const int bz = (int)(local / d.row_groups);
+    const int by0 = (int)(local % d.row_groups) * d.rows;
+    const int by1 = min(d.By, by0 + d.rows);
+    if (d.bytes == 1)
+        batch_rows<uint8_t>(d, bz, by0, by1);
+    else
+        batch_rows<uint16_t>(d, bz, by0, by1);
+}
+
+// ph 1: y passes, ph 2: z passes.
+__global__ void __launch_bounds__(kWave) k_batch_scan(const BatchVol* __restrict__ vols, int count,
+                                                      int ph, int64_t total, int lines_mult) {
     __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
     const int lane = threadIdx.x;
-    for (;;) {
-        const int64_t t = (int64_t)lane0_fetch_add(&st->ticket, 1u);
-        if (t >= total) break;
-        if (counter_read(&st->error) != 0u) break;
-        // locate (phase, volume) of ticket t
-        int ph = 2;
-        while (ph > 0 && t < vols[0].first[ph]) --ph;
-        int v = count - 1;
-        while (v > 0 && t < vols[v].first[ph]) --v;
-        const BatchVol& d = vols[v];
-        const int64_t local = t - d.first[ph];
-        if (ph == 0) {
-            if (d.bytes == 1)
-                batch_rows<uint8_t>(d, (int)local);
-            else
-                batch_rows<uint16_t>(d, (int)local);
-            mark_done(&st->done[0][v], &st->error);
-            continue;
+    const int64_t t = xcd_item(blockIdx.x);
+    if (t >= total) return;
+    const BatchVol& d = vols[batch_volume_of(vols, count, ph, t)];
+    const int64_t local = t - d.first[ph];
+    const int outer = (int)(local / d.chunks);  // z slice (phase 1) or y row (phase 2)
+    for (int j = 0; j < lines_mult; ++j) {
+        // (p, x) lines of this slice or row, 64 per pass of the wave
+        const int64_t line = ((local % d.chunks) * lines_mult + j) * kWave + lane;
+        const bool active = line < (int64_t)d.n * d.Bx;
+        const int p = active ? (int)(line / d.Bx) : 0;
+        const int x = active ? (int)(line % d.Bx) : 0;
+        int64_t base, stride;
+        int m;
+        if (ph == 1) {
+            base = (int64_t)p * d.G + (int64_t)outer * d.Bx * d.By + x;
+            stride = d.Bx;
+            m = d.By;
+        } else {
+            base = (int64_t)p * d.G + (int64_t)outer * d.Bx + x;
+            stride = (int64_t)d.Bx * d.By;
+            m = d.Bz;
         }
-        if (!wait_done(&st->done[ph - 1][v], (uint32_t)d.items[ph - 1], &st->error, spin_limit)) break;
-        const int outer = (int)(local / d.chunks);  // z slice (phase 1) or y row (phase 2)
-        for (int j = 0; j < lines_mult; ++j) {
-            // (p, x) lines of this slice or row, 64 per pass of the wave
-            const int64_t line = ((local % d.chunks) * lines_mult + j) * kWave + lane;
-            const bool active = line < (int64_t)d.n * d.Bx;
-            const int p = active ? (int)(line / d.Bx) : 0;
-            const int x = active ? (int)(line % d.Bx) : 0;
-            int64_t base, stride;
-            int m;
-            if (ph == 1) {
-                base = (int64_t)p * d.G + (int64_t)outer * d.Bx * d.By + x;
-                stride = d.Bx;
-                m = d.By;
-            } else {
-                base = (int64_t)p * d.G + (int64_t)outer * d.Bx + x;
-                stride = (int64_t)d.Bx * d.By;
-                m = d.Bz;
-            }
-            if (m > 1) {
-                uint8_t* q = d.pdms + (active ? base : 0);
-                clear_table<uint8_t>(tbl);
-                __builtin_amdgcn_wave_barrier();
-                one_sided_global<uint8_t, 16>(q, stride, m, active, tbl);
-                __builtin_amdgcn_wave_barrier();
-                clear_table<uint8_t>(tbl);
-                __builtin_amdgcn_wave_barrier();
-                one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
-            }
+        if (m > 1) {
+            uint8_t* q = d.pdms + (active ? base : 0);
+            clear_table<uint8_t>(tbl);
+            __builtin_amdgcn_wave_barrier();
+            one_sided_global<uint8_t, 16>(q, stride, m, active, tbl);
+            __builtin_amdgcn_wave_barrier();
+            clear_table<uint8_t>(tbl);
+            __builtin_amdgcn_wave_barrier();
+            one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
         }
-        mark_done(&st->done[ph][v], &st->error);
     }
 }
 
-// Copies descriptor bytes carried in kernel arguments to device memory and
-// zeroes the build state; run before k_batch_build on the same stream.
+// Copies descriptor bytes carried in kernel arguments to device memory; run
+// before the batched build kernels on the same stream.
 struct UploadChunk {
     int32_t bytes;
     int32_t pad[3];
@@ -1068,10 +1039,6 @@ struct UploadChunk {
 __global__ void __launch_bounds__(256) k_upload(uint8_t* __restrict__ dst, UploadChunk c) {
     for (int i = threadIdx.x; i < c.bytes / 16; i += blockDim.x)
         reinterpret_cast<uint4*>(dst)[i] = c.data[i];
-}
-
-__global__ void __launch_bounds__(256) k_zero(uint32_t* __restrict__ p, int words) {
-    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1241,8 +1208,7 @@ hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
-                              BatchState* d_state, int64_t total, int waves, uint32_t spin_limit,
-                              int lines_mult, hipStream_t s) {
+                              const int64_t totals[3], int lines_mult, hipStream_t s) {
     static_assert(sizeof(BatchVol) % 16 == 0, "descriptor size");
     const uint8_t* src = reinterpret_cast<const uint8_t*>(h_vols);
     const int64_t bytes = (int64_t)count * (int64_t)sizeof(BatchVol);
@@ -1253,9 +1219,16 @@ hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vol
         memcpy(c.data, src + off, (size_t)nb);
         k_upload<<<1, 256, 0, s>>>(reinterpret_cast<uint8_t*>(d_vols) + off, c);
     }
-    k_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(d_state), (int)(sizeof(BatchState) / 4));
-    k_batch_build<<<(unsigned)waves, kWave, 0, s>>>(d_vols, count, d_state, total, spin_limit,
-                                                     lines_mult);
+    constexpr int64_t span = (int64_t)kXcds * kXcdRun;
+    for (int ph = 0; ph < 3; ++ph) {
+        if (totals[ph] <= 0) continue;
+        const int64_t grid = (totals[ph] + span - 1) / span * span;
+        if (grid > INT32_MAX) return hipErrorInvalidValue;
+        if (ph == 0)
+            k_batch_rows<<<(unsigned)grid, kWave, 0, s>>>(d_vols, count, totals[0]);
+        else
+            k_batch_scan<<<(unsigned)grid, kWave, 0, s>>>(d_vols, count, ph, totals[ph], lines_mult);
+    }
     return hipGetLastError();
 }
 

@@ -52,19 +52,14 @@ struct BatchVol {
     void* bmax;
     uint8_t* pdms;
     int64_t G;
-    int64_t first[3];  // first ticket of each phase (bricks+x, y, z) of this volume
-    int32_t items[3];  // tickets per phase
+    int64_t first[3];  // first item of this volume in each phase (rows, y, z)
+    int32_t items[3];  // items per phase
     int32_t chunks;    // items per slice (y) or row (z): ceil(n*Bx / (64*lines_mult))
-    int32_t nx, ny, nz, Bx, By, Bz, bytes, n, levels, vec_ok, store_vec, pad;
+    int32_t nx, ny, nz, Bx, By, Bz, bytes, n, levels, vec_ok, store_vec;
+    int32_t rows;        // brick rows per first-phase item
+    int32_t row_groups;  // first-phase items per z slice: ceil(By / rows)
+    int32_t pad1[6];
     int32_t bounds[257];
-    int32_t pad2[3];
-};
-
-// Device workspace of the persistent build, zeroed by the launcher.
-struct BatchState {
-    uint32_t ticket;       // next work item
-    uint32_t error;        // 1 when a wait ran out of spins
-    uint32_t done[3][PDM_BATCH_MAX_ITEMS];  // finished items per phase and volume
 };
 
 struct BrickArgs {
@@ -107,12 +102,10 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
 hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s);
-// Uploads `count` descriptors into d_vols and zeroes d_state, then runs the
-// persistent build over `total` tickets with `waves` one-wave work-groups;
-// a y/z item covers 64*lines_mult lines.
+// Uploads `count` descriptors into d_vols, then runs the three grouped build
+// launches over totals[ph] items each; a y/z item covers 64*lines_mult lines.
 hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
-                              BatchState* d_state, int64_t total, int waves, uint32_t spin_limit,
-                              int lines_mult, hipStream_t s);
+                              const int64_t totals[3], int lines_mult, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
 hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
                           int vec, hipStream_t s);

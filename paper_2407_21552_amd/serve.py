@@ -192,14 +192,19 @@ class Server:
         return len(batch)
 
     def drain(self, timeout: float = 60.0) -> None:
+        """Serve until the queue is empty and every launch has completed.
+        Polls without sleeping: a sleep's wake-up slack (tens of
+        microseconds and more) would add to every request's latency."""
         end = self.now() + timeout
         while (self.queue or self.inflight) and self.now() < end:
-            if self.tick() == 0:
-                time.sleep(0.0002)
+            self.tick()
 
-    def run(self, schedule: List[Request], timeout: float = 120.0) -> None:
+    def run(self, schedule: List[Request], timeout: float = 120.0,
+            idle_sleep_s: float = 0.0005) -> None:
         """Feed requests at their arrival times (server clock) and serve
-        until all are done."""
+        until all are done.  The loop polls while work is queued or in flight
+        and sleeps only when idle with the next arrival more than
+        `idle_sleep_s` away (waking that long before it)."""
         schedule = sorted(schedule, key=lambda r: r.arrival)
         i = 0
         end = self.now() + timeout
@@ -208,8 +213,11 @@ class Server:
             while i < len(schedule) and schedule[i].arrival <= t:
                 self.submit(schedule[i])
                 i += 1
-            if self.tick() == 0:
-                time.sleep(0.0001)
+            self.tick()
+            if not self.queue and not self.inflight and i < len(schedule):
+                gap = schedule[i].arrival - self.now()
+                if gap > 2 * idle_sleep_s:
+                    time.sleep(gap - idle_sleep_s)
 
     def report(self) -> dict:
         lat = np.array([r.done - r.arrival for r in self.completed]) if self.completed else np.zeros(0)
@@ -297,13 +305,13 @@ class GpuExecutor(Executor):
     def launch(self, batch):
         import paper_2407_21552_amd as pdm
         torch = self.torch
-        items = []
+        entries = []
         for h, alpha, req in batch:
             out = h.outs[h.next_out]
             h.next_out = (h.next_out + 1) % len(h.outs)
             req.result = out
-            items.append((h.vol.desc, h.vol.pdms, h.vol.bounds, alpha, out))
-        pdm.batch_tf_update(items, self.update_stream)
+            entries.append((h.vol.prepared, alpha, out))
+        pdm.batch_tf_update_prepared(entries, self.update_stream)
         ev = torch.cuda.Event()
         ev.record(self.update_stream)
         return ev

@@ -179,3 +179,5 @@ def test_batch_build_validation(lib):
     assert lib.pdm_batch_build(arr2, 1, FAKE, need, None, NULL) == L.PDM_E_UNSUPPORTED
     bad_cfg = ctypes.pointer(L.BatchConfig(0, 17, 0, 0))
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_cfg, NULL) == L.PDM_E_INVAL
+    bad_rows = ctypes.pointer(L.BatchConfig(257, 1, 0, 0))
+    assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_rows, NULL) == L.PDM_E_INVAL

@@ -303,20 +303,31 @@ def test_batch_tf_update_matches_oracle(pdm, orc):
         pdm.tf_update(v.desc, v.pdms, v.bounds, items[k][3], single)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(pdm.from_device(single).reshape(-1), pdm.from_device(out))
+    # the prepared-volume path gives the same masks and maps
+    outs2 = [torch.empty(v.G, dtype=torch.uint8, device="cuda") for v, _ in vols]
+    masks2 = pdm.batch_tf_update_prepared(
+        [(v.prepared, it[3], o) for (v, _), it, o in zip(vols, items, outs2)])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(masks2, masks)
+    for (v, out), o in zip(vols, outs2):
+        assert torch.equal(o, out)
 
 
 # ------------------------------------------------------ batched build
-@pytest.mark.parametrize("config", [None, dict(waves=64, lines_mult=4, largest_first=1),
-                                    dict(waves=7, lines_mult=1)],
-                         ids=["default", "few-waves-long-items", "seven-waves"])
+@pytest.mark.parametrize("config", [None, dict(rows_per_item=1, lines_mult=4, largest_first=1),
+                                    dict(rows_per_item=7, lines_mult=1),
+                                    dict(rows_per_item=256, lines_mult=16, largest_first=1)],
+                         ids=["default", "one-row-long-chunks", "seven-rows", "whole-slices"])
 def test_batch_build_matches_single_volume_and_oracle(pdm, orc, config):
-    """One persistent launch builds bricks and PDMs of volumes of mixed
-    dtypes, ragged sizes and partition counts; each against the oracle."""
+    """Three grouped launches build bricks and PDMs of volumes of mixed
+    dtypes, ragged sizes and partition counts, including grid axes of 1 and
+    of the 256-brick maximum; each against the oracle."""
     import torch
     specs = [((37, 29, 45), np.uint8, 256, 16), ((20, 24, 64), np.uint16, 4096, 32),
              ((9, 14, 30), np.uint8, 256, 64), ((64, 64, 64), np.uint8, 256, 8),
              ((5, 6, 7), np.uint16, 4096, 3), ((1, 1, 1), np.uint8, 256, 2),
-             ((30, 31, 33), np.uint8, 256, 200)]
+             ((30, 31, 33), np.uint8, 256, 200), ((3, 9, 1021), np.uint8, 256, 5),
+             ((1021, 5, 6), np.uint16, 4096, 4)]
     vols, items = [], []
     for k, (shape, dtype, L, n) in enumerate(specs):
         vol = blocky(shape, dtype, L, seed=200 + k)
@@ -324,14 +335,17 @@ def test_batch_build_matches_single_volume_and_oracle(pdm, orc, config):
         v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=dtype)
         vols.append((vol, v, bounds, L))
         items.append((v.desc, v.volume, v.bmin, v.bmax, bounds, v.pdms))
-    ws = torch.zeros(pdm.batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(pdm.batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
     say(f"[case] batch build of {len(items)} volumes, config {config}")
     pdm.batch_build(items, ws, config)
     torch.cuda.synchronize()
-    assert pdm.batch_error(ws) == 0
     for k, (vol, v, bounds, L) in enumerate(vols):
         bmin, bmax = orc.bricks(vol)
         np.testing.assert_array_equal(pdm.from_device(v.bmin, vol.dtype), bmin, err_msg=f"bmin {k}")
         np.testing.assert_array_equal(pdm.from_device(v.bmax, vol.dtype), bmax, err_msg=f"bmax {k}")
         np.testing.assert_array_equal(pdm.from_device(v.pdms), orc.pdms(vol, bounds, L),
                                       err_msg=f"pdms {k}")
+        single = pdm.Volume(v.volume, L, bounds, voxel_dtype=vol.dtype)
+        single.build()
+        torch.cuda.synchronize()
+        assert torch.equal(single.pdms, v.pdms) and torch.equal(single.bmax, v.bmax), k
