@@ -50,7 +50,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_21552_amd", "csrc", "pdm_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tube_tree_1024x1024x795.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tube_tree_1024x1024x795.md")
 
 # paper's numbers (RTX 4090, OpenGL), kingsnake 1024x1024x795, 64 partitions
 PAPER_CONTEXT = {
@@ -71,11 +71,13 @@ def kernel_hash() -> str:
 
 
 def load_traffic():
-    """HBM bytes per launch measured with rocprofv3 counters, valid only for
-    the kernel source they were taken on."""
+    """HBM bytes per launch measured with rocprofv3 counters (the JSON block
+    of the traffic summary), valid only for the kernel source they were
+    taken on."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_hash():
         return None
@@ -263,7 +265,12 @@ def main():
              "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
              "traffic": None, "algorithmic": launches_bytes_note}
         if traffic and name in traffic.get("kernels", {}):
-            r["traffic"] = traffic["kernels"][name]["hbm_bytes_per_launch"]
+            k = traffic["kernels"][name]
+            r["traffic"] = k["hbm_bytes_per_launch"]
+            if k.get("algorithmic_bytes_per_launch"):
+                # the counter runs' own launches (the combine's |S| differs per TF)
+                r["traffic_vs_algorithmic"] = round(k["hbm_bytes_per_launch"]
+                                                    / k["algorithmic_bytes_per_launch"], 4)
         return r
 
     total_by_kernel = {
