@@ -410,6 +410,10 @@ def run_batched(args):
                    "pdm_bytes": sum(v.n * v.G for v in vols)},
         "build": {"per_volume_loop_ms": round(loop_ms, 3), "batched_tuned_ms": round(batch_ms, 3),
                   "batched_default_ms": round(default_ms, 3),
+                  "best_grouped_ms": round(min(t for k, t in table.items()
+                                               if '"single_launch": 0' in k), 3),
+                  "best_single_launch_ms": round(min(t for k, t in table.items()
+                                                     if '"single_launch": 1' in k), 3),
                   "speedup_vs_loop": round(loop_ms / batch_ms, 3),
                   "GBps_batched": round(build_bytes / (batch_ms * 1e-3) / 1e9, 1),
                   "tuned_config": best, "identical_to_loop": same_build,

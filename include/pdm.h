@@ -153,16 +153,21 @@ pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
 /* Batched one-time initialisation: pdm_build_bricks + pdm_build_partitions
  * (Sec. 3.1: brick [min,max], then every partition's POM and its distance
  * transform) for up to PDM_BATCH_MAX volumes of different sizes, dtypes and
- * partition counts in three grouped launches, each covering every volume:
- * bricks + POM x distances per group of brick rows, then all y passes, then
- * all z passes.  Results are identical to the single-volume calls.  Every
- * grid axis must be <= 256 bricks (else PDM_E_UNSUPPORTED).  Voxel values are
- * not range-checked here (pdm_build_bricks reports them).
+ * partition counts.  Three phases, each covering every volume: bricks + POM
+ * x distances per group of brick rows, then all y passes, then all z passes;
+ * either as three grouped launches or (cfg->single_launch) as ONE cooperative
+ * launch of resident work-groups with a grid barrier between the phases.
+ * Results are identical to the single-volume calls.  Every grid axis must be
+ * <= 256 bricks (else PDM_E_UNSUPPORTED).  Voxel values are not range-checked
+ * here (pdm_build_bricks reports them).
  *
  * d_workspace: device memory of pdm_batch_workspace_bytes(count) bytes,
- * 16-byte aligned, owned by the caller; it receives the volume descriptors
- * and must not be used by another call until the stream has passed this
- * build.
+ * 16-byte aligned, owned by the caller; it receives the barrier state and the
+ * volume descriptors and must not be used by another call until the stream
+ * has passed this build.  Its first 4 bytes are an error word, zeroed by the
+ * call: non-zero once the stream has passed the build means a single-launch
+ * barrier wait gave up after its time limit (never expected; the outputs
+ * are then incomplete).  The grouped launches leave it zero.
  * cfg: nullable tuning knobs (see pdm_batch_config); results do not depend on
  * them. */
 typedef struct {
@@ -176,10 +181,12 @@ typedef struct {
 } pdm_batch_volume;
 
 typedef struct {
-    int32_t rows_per_item;  /* brick rows per first-phase work item, 1..256; 0 = 4 */
+    int32_t rows_per_item;  /* wave passes per first-phase work item, 1..256; 0 = 2 (a
+                               pass covers 64/W brick rows, W = lanes per row, the
+                               power of two >= Bx/4) */
     int32_t lines_mult;     /* 64-line groups per y/z work item, 1..16; 0 = 1 */
     int32_t largest_first;  /* 1: order the volumes' items by decreasing work */
-    int32_t reserved;
+    int32_t single_launch;  /* 0: three grouped launches; 1: one cooperative launch */
 } pdm_batch_config;
 
 size_t pdm_batch_workspace_bytes(int32_t count);

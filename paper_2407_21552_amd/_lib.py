@@ -54,7 +54,7 @@ class BatchVolume(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("rows_per_item", ctypes.c_int32), ("lines_mult", ctypes.c_int32),
-                ("largest_first", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("largest_first", ctypes.c_int32), ("single_launch", ctypes.c_int32)]
 
 
 class GridDesc(ctypes.Structure):
@@ -405,7 +405,8 @@ def batch_build(items, workspace, config=None, stream=None) -> None:
     items: sequence of (desc, volume, bmin, bmax, bounds, pdms); workspace: a
     uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more
     (it receives the descriptors; keep it until the stream has passed);
-    config: None or dict(rows_per_item=, lines_mult=, largest_first=)."""
+    config: None or dict(rows_per_item=, lines_mult=, largest_first=,
+    single_launch=)."""
     count = len(items)
     if not 1 <= count <= BATCH_MAX:
         raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
@@ -431,8 +432,15 @@ def batch_build(items, workspace, config=None, stream=None) -> None:
     if config is not None:
         cfg = ctypes.pointer(BatchConfig(int(config.get("rows_per_item", 0)),
                                          int(config.get("lines_mult", 0)),
-                                         int(config.get("largest_first", 0)), 0))
+                                         int(config.get("largest_first", 0)),
+                                         int(config.get("single_launch", 0))))
     _check(lib().pdm_batch_build(arr, count, _dev_ptr(workspace, ws_bytes, "workspace"),
                                  ws_bytes, cfg, _stream(stream)), "pdm_batch_build")
     del keep
 
+
+def batch_error(workspace) -> int:
+    """The error word of a batch-build workspace (synchronises with the
+    device): non-zero means a single-launch barrier wait gave up."""
+    import torch
+    return int(workspace[0:4].view(torch.int32).item())

@@ -1,13 +1,15 @@
 """Autotuner for the batched build's launch shape.
 
-The batched build (pdm_batch_build) has three knobs that change its speed
-but not its result: the brick rows per first-phase work item, the number of
-64-line groups per y/z work item, and whether the largest volumes' items
-come first.  `tune_batch_build` times every candidate on the actual batch
-(HIP events on the launch stream, median of a few runs, after one warm-up)
-and caches the fastest configuration under a signature of the batch (volume shapes, dtypes,
-partition counts) and the device name.  The brick size is fixed at 4 by the
-method; only these launch shapes are tuned.
+The batched build (pdm_batch_build) has four knobs that change its speed
+but not its result: three grouped launches or one cooperative launch, the
+brick rows per first-phase work item, the number of 64-line groups per y/z
+work item, and whether the largest volumes' items come first.
+`tune_batch_build` times every candidate on the actual batch (HIP events on
+the launch stream, median of a few runs, after one warm-up, checking the
+workspace error word) and caches the fastest configuration under a
+signature of the batch (volume shapes, dtypes, partition counts) and the
+device name.  The brick size is fixed at 4 by the method; only these launch
+shapes are tuned.
 """
 from __future__ import annotations
 
@@ -17,8 +19,8 @@ import os
 
 from . import _lib
 
-CANDIDATES = [dict(rows_per_item=r, lines_mult=m, largest_first=lf)
-              for r in (1, 2, 4, 8) for m in (1, 2, 4) for lf in (0, 1)]
+CANDIDATES = [dict(single_launch=sl, rows_per_item=r, lines_mult=m, largest_first=lf)
+              for sl in (0, 1) for r in (1, 2, 4) for m in (1, 2, 4) for lf in (0, 1)]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pdm_autotune.json")
 
@@ -58,6 +60,8 @@ def time_batch_build(items, workspace, config, reps: int = 3, stream=None) -> fl
         _lib.batch_build(items, workspace, config, s)
         b.record(s)
         b.synchronize()
+        if _lib.batch_error(workspace) != 0:
+            raise _lib.PdmError(_lib.PDM_E_DEVICE, "single-launch batched build: a barrier wait gave up")
         times.append(a.elapsed_time(b))
     times.sort()
     return times[len(times) // 2]

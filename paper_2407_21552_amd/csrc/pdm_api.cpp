@@ -82,7 +82,6 @@ pdm_status plain_args(const pdm_volume* v, const void* d_volume, const float* h_
     a->bytes = v->dtype;
     a->nwords = (v->levels + 31) / 32;
     a->levels = v->levels;
-    a->vec_ok = ((int64_t)v->nx * v->dtype) % 16 == 0 && aligned(d_volume, 16);
     a->store_vec = g.bx % 4 == 0 && aligned(d_dist, 4);
     return PDM_OK;
 }
@@ -128,7 +127,6 @@ pdm_status pdm_build_bricks(const pdm_volume* v, const void* d_volume, void* d_b
     a.Bz = g.bz;
     a.bytes = v->dtype;
     a.levels = v->levels;
-    a.vec_ok = ((int64_t)v->nx * v->dtype) % 16 == 0 && aligned(d_volume, 16);
     a.store_vec = g.bx % 4 == 0 && aligned(d_bmin, 4 * v->dtype) && aligned(d_bmax, 4 * v->dtype);
     // the range flag is only needed when the dtype can hold values >= levels
     if (v->levels == (v->dtype == PDM_U8 ? 256 : 65536)) a.range_err = nullptr;
@@ -231,7 +229,7 @@ pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
 
 size_t pdm_batch_workspace_bytes(int32_t count) {
     if (count < 1 || count > PDM_BATCH_MAX) return 0;
-    return (size_t)count * sizeof(pdm::BatchVol);
+    return sizeof(pdm::BatchSync) + (size_t)count * sizeof(pdm::BatchVol);
 }
 
 pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
@@ -243,10 +241,11 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         return PDM_E_INVAL;
     pdm_batch_config c = {0, 0, 0, 0};
     if (cfg != nullptr) c = *cfg;
-    if (c.rows_per_item < 0 || c.rows_per_item > 256 || c.lines_mult < 0 || c.lines_mult > 16)
+    if (c.rows_per_item < 0 || c.rows_per_item > 256 || c.lines_mult < 0 || c.lines_mult > 16 ||
+        c.single_launch < 0 || c.single_launch > 1)
         return PDM_E_INVAL;
     if (c.lines_mult == 0) c.lines_mult = 1;
-    if (c.rows_per_item == 0) c.rows_per_item = 4;
+    if (c.rows_per_item == 0) c.rows_per_item = 2;
     // host staging of the descriptors (copied to the workspace by the launcher)
     pdm::BatchVol tmp[PDM_BATCH_MAX];
     pdm::BatchVol vols[PDM_BATCH_MAX];
@@ -278,13 +277,17 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         d.bytes = it.v->dtype;
         d.n = it.n;
         d.levels = it.v->levels;
-        d.vec_ok = ((int64_t)it.v->nx * it.v->dtype) % 16 == 0 && aligned(it.d_volume, 16);
         d.store_vec = g.bx % 4 == 0 && aligned(it.d_pdms, 4);
         for (int32_t p = 0; p <= it.n; ++p) d.bounds[p] = it.h_bounds[p];
         const int64_t lines = (int64_t)it.n * g.bx;
         d.chunks = (int32_t)((lines + 64 * c.lines_mult - 1) / (64 * c.lines_mult));
-        d.rows = c.rows_per_item;
-        d.row_groups = (g.by + c.rows_per_item - 1) / c.rows_per_item;
+        // first phase: a row takes the power-of-two lane count >= Bx/4, so
+        // narrow rows share a wave; an item is rows_per_item wave passes
+        int32_t lanes = 1;
+        while (4 * lanes < g.bx) lanes *= 2;
+        d.row_lanes = lanes;
+        d.rows = c.rows_per_item * (64 / lanes);
+        d.row_groups = (g.by + d.rows - 1) / d.rows;
         d.items[0] = g.bz * d.row_groups;
         d.items[1] = g.by > 1 ? g.bz * d.chunks : 0;  // a pass over lines of 1 brick is the identity
         d.items[2] = g.bz > 1 ? g.by * d.chunks : 0;
@@ -309,8 +312,11 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         }
     for (int ph = 0; ph < 3; ++ph)
         if (totals[ph] > INT32_MAX - 64) return PDM_E_UNSUPPORTED;
-    pdm::BatchVol* dv = static_cast<pdm::BatchVol*>(d_workspace);
-    return from_hip(pdm::launch_batch_build(vols, count, dv, totals, c.lines_mult, stream));
+    uint8_t* ws = static_cast<uint8_t*>(d_workspace);
+    pdm::BatchSync* sync = reinterpret_cast<pdm::BatchSync*>(ws);
+    pdm::BatchVol* dv = reinterpret_cast<pdm::BatchVol*>(ws + sizeof(pdm::BatchSync));
+    return from_hip(pdm::launch_batch_build(vols, count, dv, sync, totals, c.lines_mult,
+                                            c.single_launch, stream));
 }
 
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
@@ -355,7 +361,6 @@ pdm_status pdm_pom_exact_distance_x(const pdm_volume* v, const void* d_volume,
     a.bytes = v->dtype;
     a.n = n;
     a.levels = v->levels;
-    a.vec_ok = ((int64_t)v->nx * v->dtype) % 16 == 0 && aligned(d_volume, 16);
     a.store_vec = g.bx % 4 == 0 && aligned(d_pdms, 4);
     return from_hip(pdm::launch_pom_exact_x(a, b, stream));
 }

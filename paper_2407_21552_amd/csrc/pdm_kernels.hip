@@ -60,19 +60,41 @@ __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b 
 // voxels x in [16q, 16q+16), y in [4by, 4by+4), z in [4bz, 4bz+4), clipped to
 // the volume.  Results for bricks outside the grid are unspecified.
 // ---------------------------------------------------------------------------
+// 16 bytes from any byte address: one vector load (the hardware serves
+// unaligned vector loads), so voxel rows of any width and offset stream in
+// 16-byte pieces.
+__device__ __forceinline__ uint4 load16(const void* p) {
+    uint4 w;
+    __builtin_memcpy(&w, p, 16);
+    return w;
+}
+
+// Pointers typed in the global address space.  Kernel arguments are known to
+// be global; pointers read from a descriptor are not, and would compile to
+// flat accesses, which also count against the LDS wait counter and so stall
+// the LDS-paced scan loops.  The batched kernels cast their descriptor
+// pointers to these types; the helpers below take either kind.
+#define PDM_GLB __attribute__((address_space(1)))
+
+__device__ __forceinline__ uint4 load16(const PDM_GLB void* p) {
+    uint4 w;
+    __builtin_memcpy(&w, p, 16);
+    return w;
+}
+
 template <typename T>
 struct QuadMinMax {
     uint32_t mn[4], mx[4];
 };
 
-template <typename T>
-__device__ __forceinline__ QuadMinMax<T> quad_minmax(const T* __restrict__ vol, int nx, int ny,
-                                                     int nz, int q, int by, int bz, bool vec_ok) {
+template <typename T, typename VP>
+__device__ __forceinline__ QuadMinMax<T> quad_minmax(VP __restrict__ vol, int nx, int ny, int nz,
+                                                     int q, int by, int bz) {
     QuadMinMax<T> r;
     const int x0 = 16 * q;
     const int z0 = 4 * bz, y0 = 4 * by;
     const int zn = min(4, nz - z0), yn = min(4, ny - y0);
-    if (vec_ok && x0 + 16 <= nx) {
+    if (x0 + 16 <= nx) {
         if constexpr (sizeof(T) == 1) {
             // even/odd byte lanes held as packed u16 pairs, one pair per brick
             uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
@@ -83,7 +105,7 @@ __device__ __forceinline__ QuadMinMax<T> quad_minmax(const T* __restrict__ vol, 
                 for (int yy = 0; yy < 4; ++yy) {
                     if (yy < yn) {
                         const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
-                        const uint4 w = *reinterpret_cast<const uint4*>(vol + off);
+                        const uint4 w = load16(vol + off);
                         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
@@ -113,8 +135,7 @@ __device__ __forceinline__ QuadMinMax<T> quad_minmax(const T* __restrict__ vol, 
                 for (int yy = 0; yy < 4; ++yy) {
                     if (yy < yn) {
                         const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
-                        const uint4* p = reinterpret_cast<const uint4*>(vol + off);
-                        const uint4 a = p[0], b = p[1];
+                        const uint4 a = load16(vol + off), b = load16(vol + off + 8);
                         const uint32_t ws[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
@@ -161,7 +182,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int nx, int ny, int nz,
                                                 int Bx, int By, int Bz, int Qx, T* __restrict__ bmin,
                                                 T* __restrict__ bmax, int levels,
-                                                int32_t* __restrict__ range_err, int vec_ok,
+                                                int32_t* __restrict__ range_err,
                                                 int store_vec) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)Qx * By * Bz;
@@ -169,7 +190,7 @@ __global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int n
     const int q = (int)(t % Qx);
     const int64_t row = t / Qx;
     const int by = (int)(row % By), bz = (int)(row / By);
-    const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0);
+    const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz);
     const int64_t base = row * Bx + 4 * q;
     const int nb = min(4, Bx - 4 * q);
     if (range_err != nullptr) {
@@ -211,6 +232,8 @@ __global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int n
 __device__ __forceinline__ uint32_t x_distances(uint32_t o, int lane, int xs, int prev_last,
                                                 int next_first) {
     const uint64_t any = __ballot(o != 0u);
+    // no occupied brick in the segment or beyond it: every distance is capped
+    if (any == 0ull && prev_last == -kNone && next_first == kNone) return 0xFFFFFFFFu;
     const int hik = o ? 31 - __clz(o) : 0;
     const int lok = o ? __ffs(o) - 1 : 0;
     const uint64_t below = any & ((1ull << lane) - 1ull);
@@ -236,6 +259,43 @@ __device__ __forceinline__ uint32_t x_distances(uint32_t o, int lane, int xs, in
     return packed;
 }
 
+// Distances along x for short rows packed into one wave: lane L holds the
+// occupancy nibble of bricks 4r .. 4r+3 (r = L mod W) of the wave's row
+// floor(L / W), W a power of two from 1 to 64; a row has at most 4W bricks
+// and nothing outside it counts.  Returns the 4 clamped distances packed into
+// bytes.  Must be called by the whole wave.
+__device__ __forceinline__ uint32_t x_distances_rows(uint32_t o, int lane, int W) {
+    const uint64_t any = __ballot(o != 0u);
+    if (any == 0ull) return 0xFFFFFFFFu;  // no occupied brick in these rows
+    const int base = lane & ~(W - 1);
+    const uint64_t seg = W >= kWave ? ~0ull : (((1ull << W) - 1ull) << base);
+    const uint64_t mine = any & seg;
+    const uint64_t below = mine & ((1ull << lane) - 1ull);
+    const uint64_t above = (lane == kWave - 1) ? 0ull : (mine & (~0ull << (lane + 1)));
+    const int hik = o ? 31 - __clz(o) : 0;
+    const int lok = o ? __ffs(o) - 1 : 0;
+    const int src_l = below ? 63 - __clzll((long long)below) : lane;
+    const int src_r = above ? __ffsll((unsigned long long)above) - 1 : lane;
+    const int hi_l = __shfl(hik, src_l, kWave);
+    const int lo_r = __shfl(lok, src_r, kWave);
+    const int r = lane - base;
+    const int left_lane = below ? 4 * (src_l - base) + hi_l : -kNone;
+    const int right_lane = above ? 4 * (src_r - base) + lo_r : kNone;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = 4 * r + k;
+        const uint32_t ml = o & ((2u << k) - 1u);
+        const uint32_t mr = o & (0xFu & ~((1u << k) - 1u));
+        const int lp = ml ? 4 * r + (31 - __clz(ml)) : left_lane;
+        const int rp = mr ? 4 * r + (__ffs(mr) - 1) : right_lane;
+        int d = min(x - lp, rp - x);
+        d = min(d, 255);
+        packed |= (uint32_t)d << (8 * k);
+    }
+    return packed;
+}
+
 // Position of the first / last occupied brick of a segment (wave-uniform).
 __device__ __forceinline__ int seg_first(uint32_t o, int xs) {
     const uint64_t any = __ballot(o != 0u);
@@ -252,10 +312,18 @@ __device__ __forceinline__ int seg_last(uint32_t o, int xs) {
     return any ? xs + 4 * src + v : -kNone;
 }
 
-__device__ __forceinline__ void store_quad(uint8_t* __restrict__ dst, int64_t idx, int nb,
+__device__ __forceinline__ void store_u32(uint8_t* p, uint32_t v) {
+    *reinterpret_cast<uint32_t*>(p) = v;
+}
+__device__ __forceinline__ void store_u32(PDM_GLB uint8_t* p, uint32_t v) {
+    *reinterpret_cast<PDM_GLB uint32_t*>(p) = v;
+}
+
+template <typename DP>
+__device__ __forceinline__ void store_quad(DP __restrict__ dst, int64_t idx, int nb,
                                            uint32_t packed, bool vec) {
     if (vec && nb == 4) {
-        *reinterpret_cast<uint32_t*>(dst + idx) = packed;
+        store_u32(dst + idx, packed);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -347,7 +415,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int nx, int ny, int nz,
                                                  int Bx, int By, int64_t rows, AlphaBits bits,
                                                  int nwords, int levels, uint8_t* __restrict__ dist,
-                                                 int vec_ok, int store_vec) {
+                                                 int store_vec) {
     __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
     __shared__ uint16_t s_pre[PDM_ALPHA_WORDS + 1];
     __shared__ uint8_t s_nib[4][kMaxSegs][kWave];
@@ -373,7 +441,7 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
         const int q = s * kWave + lane;  // quad index within the row
         uint32_t o = 0;
         if (4 * q < Bx) {
-            const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0);
+            const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz);
             const int nb = min(4, Bx - 4 * q);
             // voxels >= levels break the precondition; clamping keeps the
             // bitmap lookups inside the table
@@ -406,26 +474,25 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 // (bz, by) that lies inside the volume (k = brick within the quad).
 template <typename T, typename F>
 __device__ __forceinline__ void quad_voxels(const T* __restrict__ vol, int nx, int ny, int nz, int q,
-                                            int by, int bz, bool vec_ok, F f) {
+                                            int by, int bz, F f) {
     const int x0 = 16 * q;
     const int z0 = 4 * bz, y0 = 4 * by;
     const int zn = min(4, nz - z0), yn = min(4, ny - y0);
-    if (vec_ok && x0 + 16 <= nx) {
+    if (x0 + 16 <= nx) {
         for (int zz = 0; zz < zn; ++zz) {
 #pragma unroll
             for (int yy = 0; yy < 4; ++yy) {
                 if (yy < yn) {
                     const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
                     if constexpr (sizeof(T) == 1) {
-                        const uint4 w = *reinterpret_cast<const uint4*>(vol + off);
+                        const uint4 w = load16(vol + off);
                         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
                         for (int k = 0; k < 4; ++k)
 #pragma unroll
                             for (int b = 0; b < 4; ++b) f(k, (ws[k] >> (8 * b)) & 0xFFu);
                     } else {
-                        const uint4* p = reinterpret_cast<const uint4*>(vol + off);
-                        const uint4 a = p[0], c = p[1];
+                        const uint4 a = load16(vol + off), c = load16(vol + off + 8);
                         const uint32_t ws[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
@@ -462,7 +529,7 @@ __global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, 
                                                      int nz, int Bx, int By, int64_t rows,
                                                      Bounds bounds, int n, int levels,
                                                      uint8_t* __restrict__ pdms, int64_t G,
-                                                     int vec_ok, int store_vec) {
+                                                     int store_vec) {
     __shared__ uint8_t s_part[PDM_EXACT_MAX_LEVELS];
     // partition p paints its intensities [bounds[p], bounds[p+1])
     for (int p = threadIdx.x; p < n; p += blockDim.x)
@@ -480,7 +547,7 @@ __global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, 
         for (int w = 0; w < NW; ++w) mk[k][w] = 0u;
     const uint32_t top = (uint32_t)levels - 1u;  // voxels >= levels break the precondition
     if (4 * lane < Bx) {
-        quad_voxels<T>(vol, nx, ny, nz, lane, by, bz, vec_ok != 0, [&](int k, uint32_t val) {
+        quad_voxels<T>(vol, nx, ny, nz, lane, by, bz, [&](int k, uint32_t val) {
             const uint32_t pid = s_part[umin(val, top)];
             const uint32_t bit = 1u << (pid & 31u);
 #pragma unroll
@@ -509,7 +576,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol, int nx, int ny,
                                                        int nz, int Bx, int By, int64_t rows,
                                                        AlphaBits bits, int nwords, int levels,
-                                                       uint8_t* __restrict__ dist, int vec_ok,
+                                                       uint8_t* __restrict__ dist,
                                                        int store_vec) {
     __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
     __shared__ uint8_t s_nib[4][kMaxSegs][kWave];
@@ -527,7 +594,7 @@ __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol
         const int q = s * kWave + lane;
         uint32_t o = 0;
         if (4 * q < Bx) {
-            quad_voxels<T>(vol, nx, ny, nz, q, by, bz, vec_ok != 0, [&](int k, uint32_t val) {
+            quad_voxels<T>(vol, nx, ny, nz, q, by, bz, [&](int k, uint32_t val) {
                 const uint32_t v = umin(val, top);
                 o |= ((s_words[v >> 5] >> (v & 31u)) & 1u) << k;
             });
@@ -649,8 +716,8 @@ __device__ __forceinline__ void one_sided_lds(uint8_t* col, int cs, int m, P* __
 
 // The same pass over a line in global memory, p[k * step] (lines longer
 // than the LDS tile); `active` false lanes only keep the wave in step.
-template <typename P, int CH>
-__device__ __forceinline__ void one_sided_global(uint8_t* p, int64_t step, int m, bool active,
+template <typename P, int CH, typename BP>
+__device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool active,
                                                  P* __restrict__ tbl) {
     const int lane = threadIdx.x;
     int v = active ? (int)p[0] : 0;
@@ -677,6 +744,21 @@ __device__ __forceinline__ void one_sided_global(uint8_t* p, int64_t step, int m
 }
 #undef PDM_SCAN_STEP
 
+// Work-groups are handed to the 8 XCDs round-robin (work-group b runs on XCD
+// b % 8).  xcd_item maps work-group b to a work item so that runs of kXcdRun
+// consecutive items land on one XCD at about the same time: neighbouring
+// 64-line tiles of a row share 128-byte cache lines, and under one L2 the
+// second tile finds the line the first one fetched.  The grid is rounded up
+// to a multiple of kXcds * kXcdRun; work-groups past the last item return.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 4;
+constexpr int64_t kXcdSpan = (int64_t)kXcds * kXcdRun;
+
+__device__ __forceinline__ int64_t xcd_item(int64_t b) {
+    const int64_t r = b % kXcdSpan;
+    return (b - r) + (r % kXcds) * kXcdRun + r / kXcds;
+}
+
 // Line l of a pass: x fastest, then the other in-grid axis (`inner` values
 // with step `plane`), then the grid index.
 __device__ __forceinline__ int64_t line_offset(int64_t l, int Bx, int inner, int64_t plane,
@@ -698,7 +780,8 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_axis(uint8_t* __restrict__ 
     __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
     __shared__ __align__(16) uint8_t tile[kMaxLine * kScanLanes];
     const int lane = threadIdx.x;
-    const int64_t l0 = (int64_t)blockIdx.x * kScanLanes;
+    const int64_t l0 = xcd_item(blockIdx.x) * kScanLanes;
+    if (l0 >= lines) return;
     const int64_t l = l0 + lane;
     const bool active = l < lines;
     const int q = lane & 3;  // 16-byte quarter of a 64-byte row
@@ -742,7 +825,9 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
                                                             int64_t plane, int64_t stride, int m,
                                                             int64_t G) {
     __shared__ __align__(16) P tbl[((kRows * kPitch * sizeof(P) + 15) & ~15) / sizeof(P)];
-    const int64_t l = (int64_t)blockIdx.x * kScanLanes + threadIdx.x;
+    const int64_t l0 = xcd_item(blockIdx.x) * kScanLanes;
+    if (l0 >= lines) return;
+    const int64_t l = l0 + threadIdx.x;
     const bool active = l < lines;
     uint8_t* line = maps + (active ? line_offset(l, Bx, inner, plane, G) : 0);
     clear_table<P>(tbl);
@@ -910,18 +995,8 @@ __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
 // The items of a phase are numbered volume by volume in descriptor order
 // (first[ph] is the running prefix).  Work-groups are handed to the XCDs
 // round-robin; xcd_item maps them so that runs of kXcdRun consecutive items
-// land on one XCD, keeping neighbouring chunks, which share cache lines,
-// under one L2.
+// land on one XCD.
 // ---------------------------------------------------------------------------
-constexpr int kXcds = 8;
-constexpr int kXcdRun = 4;
-
-__device__ __forceinline__ int64_t xcd_item(int64_t b) {
-    constexpr int64_t span = (int64_t)kXcds * kXcdRun;
-    const int64_t r = b % span;
-    return (b - r) + (r % kXcds) * kXcdRun + r / kXcds;
-}
-
 // The volume holding item t of phase ph: the last descriptor whose first
 // item is <= t (volumes with no items in the phase share the next one's
 // first and are skipped by taking the last).
@@ -938,28 +1013,35 @@ __device__ __forceinline__ int batch_volume_of(const BatchVol* __restrict__ vols
     return lo;
 }
 
-// First phase for brick rows [by0, by1) of z slice bz (Bx <= 256: one
-// segment per row).
+// First phase for brick rows [by0, by1) of z slice bz.  A row of Bx <= 256
+// bricks takes W = row_lanes lanes (4 bricks each, W the power of two >=
+// Bx/4), so one wave pass covers 64/W rows.
 template <typename T>
 __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, int by1) {
     const int lane = threadIdx.x;
-    const T* vol = reinterpret_cast<const T*>(d.vol);
-    T* bmin = reinterpret_cast<T*>(d.bmin);
-    T* bmax = reinterpret_cast<T*>(d.bmax);
-    const int nb = max(0, min(4, d.Bx - 4 * lane));
-    for (int by = by0; by < by1; ++by) {
-        const int64_t rbase = ((int64_t)bz * d.By + by) * d.Bx;
+    const PDM_GLB T* vol = (const PDM_GLB T*)d.vol;
+    PDM_GLB T* bmin = (PDM_GLB T*)d.bmin;
+    PDM_GLB T* bmax = (PDM_GLB T*)d.bmax;
+    PDM_GLB uint8_t* pdms = (PDM_GLB uint8_t*)d.pdms;
+    const int W = d.row_lanes;
+    const int q = lane & (W - 1);
+    const int per = kWave / W;
+    const int nb_row = max(0, min(4, d.Bx - 4 * q));
+    for (int row0 = by0; row0 < by1; row0 += per) {
+        const int by = row0 + lane / W;
+        const int nb = by < by1 ? nb_row : 0;
+        const int64_t rbase = ((int64_t)bz * d.By + by) * d.Bx + 4 * q;
         uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         uint32_t mx[4] = {0u, 0u, 0u, 0u};
         if (nb > 0) {
-            const QuadMinMax<T> r = quad_minmax<T>(vol, d.nx, d.ny, d.nz, lane, by, bz, d.vec_ok != 0);
+            const QuadMinMax<T> r = quad_minmax<T>(vol, d.nx, d.ny, d.nz, q, by, bz);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (k < nb) {
                     mn[k] = r.mn[k];
                     mx[k] = r.mx[k];
-                    bmin[rbase + 4 * lane + k] = (T)r.mn[k];
-                    bmax[rbase + 4 * lane + k] = (T)r.mx[k];
+                    bmin[rbase + k] = (T)r.mn[k];
+                    bmax[rbase + k] = (T)r.mx[k];
                 }
         }
         for (int p = 0; p < d.n; ++p) {
@@ -967,16 +1049,14 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, i
             uint32_t o = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
-            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
-            if (nb > 0) store_quad(d.pdms + (int64_t)p * d.G, rbase + 4 * lane, nb, packed, d.store_vec);
+            const uint32_t packed = x_distances_rows(o, lane, W);
+            if (nb > 0) store_quad(pdms + (int64_t)p * d.G, rbase, nb, packed, d.store_vec);
         }
     }
 }
 
-__global__ void __launch_bounds__(kWave) k_batch_rows(const BatchVol* __restrict__ vols, int count,
-                                                      int64_t total) {
-    const int64_t t = xcd_item(blockIdx.x);
-    if (t >= total) return;
+__device__ __forceinline__ void batch_rows_item(const BatchVol* __restrict__ vols, int count,
+                                                int64_t t) {
     const BatchVol& d = vols[batch_volume_of(vols, count, 0, t)];
     const int64_t local = t - d.first[0];
     const int bz = (int)(local / d.row_groups);
@@ -988,13 +1068,10 @@ __global__ void __launch_bounds__(kWave) k_batch_rows(const BatchVol* __restrict
         batch_rows<uint16_t>(d, bz, by0, by1);
 }
 
-// ph 1: y passes, ph 2: z passes.
-__global__ void __launch_bounds__(kWave) k_batch_scan(const BatchVol* __restrict__ vols, int count,
-                                                      int ph, int64_t total, int lines_mult) {
-    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+// ph 1: y passes, ph 2: z passes of one item (64*lines_mult lines).
+__device__ __forceinline__ void batch_scan_item(const BatchVol* __restrict__ vols, int count, int ph,
+                                                int64_t t, int lines_mult, uint8_t* tbl) {
     const int lane = threadIdx.x;
-    const int64_t t = xcd_item(blockIdx.x);
-    if (t >= total) return;
     const BatchVol& d = vols[batch_volume_of(vols, count, ph, t)];
     const int64_t local = t - d.first[ph];
     const int outer = (int)(local / d.chunks);  // z slice (phase 1) or y row (phase 2)
@@ -1016,7 +1093,7 @@ __global__ void __launch_bounds__(kWave) k_batch_scan(const BatchVol* __restrict
             m = d.Bz;
         }
         if (m > 1) {
-            uint8_t* q = d.pdms + (active ? base : 0);
+            PDM_GLB uint8_t* q = (PDM_GLB uint8_t*)d.pdms + (active ? base : 0);
             clear_table<uint8_t>(tbl);
             __builtin_amdgcn_wave_barrier();
             one_sided_global<uint8_t, 16>(q, stride, m, active, tbl);
@@ -1025,6 +1102,99 @@ __global__ void __launch_bounds__(kWave) k_batch_scan(const BatchVol* __restrict
             __builtin_amdgcn_wave_barrier();
             one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
         }
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_batch_rows(const BatchVol* __restrict__ vols, int count,
+                                                      int64_t total) {
+    const int64_t t = xcd_item(blockIdx.x);
+    if (t < total) batch_rows_item(vols, count, t);
+}
+
+__global__ void __launch_bounds__(kWave) k_batch_scan(const BatchVol* __restrict__ vols, int count,
+                                                      int ph, int64_t total, int lines_mult) {
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    const int64_t t = xcd_item(blockIdx.x);
+    if (t < total) batch_scan_item(vols, count, ph, t, lines_mult, tbl);
+}
+
+// ---------------------------------------------------------------------------
+// Single-launch variant: one cooperative launch whose work-groups are all
+// resident take the three phases in turn, with a grid-wide barrier between
+// phases.  Within a phase each work-group takes items from the phase's
+// ticket counter until none is left (items differ in cost, so a static share
+// would leave work-groups idle); with lines_mult >= 2 the 64-line groups of
+// one item are neighbours in x and share cache lines in the same L2.
+//
+// Barrier: arrivals are counted cumulatively, so barrier k is complete when
+// the count reaches (k + 1) * gridDim.x; the work-group that makes it so
+// advances the generation word, the others poll it.  Stores before the
+// barrier are released at agent scope before the arrival, and acquired after
+// it.  Every control value is wave-uniform (readfirstlane) and lane-0 atomics
+// sit in plain if-blocks, so the compiler cannot move the arrival past the
+// wait.  A wait is bounded by wall-clock time (the 100 MHz real-time
+// counter): past the limit, or once another work-group has failed, the
+// work-group sets the error word and returns, so every wave exits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane0_fetch_add(uint32_t* cnt, uint32_t add) {
+    uint32_t r = 0;
+    if (threadIdx.x == 0)
+        r = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(r);
+}
+
+__device__ __forceinline__ uint32_t lane0_load(uint32_t* p) {
+    uint32_t r = 0;
+    if (threadIdx.x == 0) r = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(r);
+}
+
+__device__ __forceinline__ bool grid_barrier(BatchSync* st, uint32_t k, uint64_t limit_ticks) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t arrivals = (k + 1u) * gridDim.x;
+    const uint32_t before = lane0_fetch_add(&st->arrive, 1u);
+    bool ok = true;
+    if (before + 1u == arrivals) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&st->generation, k + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        uint32_t naps = 1;
+        while (lane0_load(&st->generation) <= k) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit_ticks || lane0_load(&st->error) != 0u) {
+                ok = false;
+                break;
+            }
+            for (uint32_t i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
+            naps = naps < 8u ? naps + 1u : 8u;
+        }
+    }
+    if (!ok && threadIdx.x == 0) __hip_atomic_fetch_or(&st->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+__global__ void __launch_bounds__(kWave) k_batch_single(const BatchVol* __restrict__ vols, int count,
+                                                        int64_t total0, int64_t total1,
+                                                        int64_t total2, int lines_mult,
+                                                        BatchSync* st, uint64_t limit_ticks) {
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    for (;;) {
+        const int64_t t = lane0_fetch_add(&st->ticket[0][0], 1u);
+        if (t >= total0) break;
+        batch_rows_item(vols, count, t);
+    }
+    if (!grid_barrier(st, 0u, limit_ticks)) return;
+    for (;;) {
+        const int64_t t = lane0_fetch_add(&st->ticket[1][0], 1u);
+        if (t >= total1) break;
+        batch_scan_item(vols, count, 1, t, lines_mult, tbl);
+    }
+    if (!grid_barrier(st, 1u, limit_ticks)) return;
+    for (;;) {
+        const int64_t t = lane0_fetch_add(&st->ticket[2][0], 1u);
+        if (t >= total2) break;
+        batch_scan_item(vols, count, 2, t, lines_mult, tbl);
     }
 }
 
@@ -1041,6 +1211,10 @@ __global__ void __launch_bounds__(256) k_upload(uint8_t* __restrict__ dst, Uploa
         reinterpret_cast<uint4*>(dst)[i] = c.data[i];
 }
 
+__global__ void __launch_bounds__(256) k_zero(uint32_t* __restrict__ p, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (host side).  Shapes are validated by the caller.
 // ---------------------------------------------------------------------------
@@ -1055,11 +1229,11 @@ hipError_t launch_bricks(const BrickArgs& a, hipStream_t s) {
     if (a.bytes == 1)
         k_bricks<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
                                              a.Bz, Qx, (uint8_t*)a.bmin, (uint8_t*)a.bmax,
-                                             a.levels, a.range_err, a.vec_ok, a.store_vec);
+                                             a.levels, a.range_err, a.store_vec);
     else
         k_bricks<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                               a.By, a.Bz, Qx, (uint16_t*)a.bmin,
-                                              (uint16_t*)a.bmax, a.levels, a.range_err, a.vec_ok,
+                                              (uint16_t*)a.bmax, a.levels, a.range_err,
                                               a.store_vec);
     return hipGetLastError();
 }
@@ -1081,12 +1255,12 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
     const unsigned nb = blocks_for(rows, 4);
     if (a.bytes == 1)
         k_plain_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
-                                              rows, bits, a.nwords, a.levels, a.dist, a.vec_ok,
+                                              rows, bits, a.nwords, a.levels, a.dist,
                                               a.store_vec);
     else
         k_plain_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                                a.By, rows, bits, a.nwords, a.levels, a.dist,
-                                               a.vec_ok, a.store_vec);
+                                               a.store_vec);
     return hipGetLastError();
 }
 
@@ -1097,7 +1271,7 @@ static hipError_t launch_pom_exact_t(const PomExactArgs& a, const Bounds& b, hip
     const int nw = (a.n + 31) / 32;
 #define PDM_LAUNCH_EXACT(NW)                                                                   \
     k_pom_exact_x<T, NW><<<nb, 256, 0, s>>>((const T*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By, rows, \
-                                            b, a.n, a.levels, a.pdms, a.G, a.vec_ok,            \
+                                            b, a.n, a.levels, a.pdms, a.G,                       \
                                             a.store_vec)
     if (nw == 1)
         PDM_LAUNCH_EXACT(1);
@@ -1121,11 +1295,11 @@ hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipSt
     if (a.bytes == 1)
         k_plain_exact_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                                     a.By, rows, bits, a.nwords, a.levels, a.dist,
-                                                    a.vec_ok, a.store_vec);
+                                                    a.store_vec);
     else
         k_plain_exact_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                                      a.By, rows, bits, a.nwords, a.levels, a.dist,
-                                                     a.vec_ok, a.store_vec);
+                                                     a.store_vec);
     return hipGetLastError();
 }
 
@@ -1157,7 +1331,8 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
                               hipStream_t s) {
     const AxisLines a = axis_lines(count, Bx, By, Bz, axis);
     const int64_t G = (int64_t)Bx * By * Bz;
-    const int64_t blocks = (a.lines + kScanLanes - 1) / kScanLanes;
+    const int64_t tiles = (a.lines + kScanLanes - 1) / kScanLanes;
+    const int64_t blocks = (tiles + kXcdSpan - 1) / kXcdSpan * kXcdSpan;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     if (a.m > kMaxLine) {
         k_dist_global<uint16_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
@@ -1208,8 +1383,10 @@ hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
-                              const int64_t totals[3], int lines_mult, hipStream_t s) {
+                              BatchSync* d_sync, const int64_t totals[3], int lines_mult,
+                              int single, hipStream_t s) {
     static_assert(sizeof(BatchVol) % 16 == 0, "descriptor size");
+    static_assert(sizeof(BatchSync) % 16 == 0, "sync size");
     const uint8_t* src = reinterpret_cast<const uint8_t*>(h_vols);
     const int64_t bytes = (int64_t)count * (int64_t)sizeof(BatchVol);
     UploadChunk c;
@@ -1219,10 +1396,33 @@ hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vol
         memcpy(c.data, src + off, (size_t)nb);
         k_upload<<<1, 256, 0, s>>>(reinterpret_cast<uint8_t*>(d_vols) + off, c);
     }
-    constexpr int64_t span = (int64_t)kXcds * kXcdRun;
+    k_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(d_sync), (int)(sizeof(BatchSync) / 4));
+    if (single) {
+        // every work-group resident at once: the occupancy of this kernel on
+        // every compute unit
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_single, kWave, 0);
+        if (e != hipSuccess) return e;
+        const int64_t grid = (int64_t)per_cu * cus;
+        if (grid < 1 || grid > INT32_MAX) return hipErrorInvalidConfiguration;
+        int64_t t0 = totals[0], t1 = totals[1], t2 = totals[2];
+        int lm = lines_mult;
+        uint64_t limit = 100ull * 1000 * 1000 * 10;  // 10 s of the 100 MHz counter
+        const BatchVol* dv = d_vols;
+        BatchSync* ds = d_sync;
+        int cnt = count;
+        void* args[] = {&dv, &cnt, &t0, &t1, &t2, &lm, &ds, &limit};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch_single), dim3((unsigned)grid),
+                                       dim3(kWave), args, 0, s);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
     for (int ph = 0; ph < 3; ++ph) {
         if (totals[ph] <= 0) continue;
-        const int64_t grid = (totals[ph] + span - 1) / span * span;
+        const int64_t grid = (totals[ph] + kXcdSpan - 1) / kXcdSpan * kXcdSpan;
         if (grid > INT32_MAX) return hipErrorInvalidValue;
         if (ph == 0)
             k_batch_rows<<<(unsigned)grid, kWave, 0, s>>>(d_vols, count, totals[0]);

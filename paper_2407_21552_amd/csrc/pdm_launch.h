@@ -55,11 +55,24 @@ struct BatchVol {
     int64_t first[3];  // first item of this volume in each phase (rows, y, z)
     int32_t items[3];  // items per phase
     int32_t chunks;    // items per slice (y) or row (z): ceil(n*Bx / (64*lines_mult))
-    int32_t nx, ny, nz, Bx, By, Bz, bytes, n, levels, vec_ok, store_vec;
+    int32_t nx, ny, nz, Bx, By, Bz, bytes, n, levels, store_vec;
     int32_t rows;        // brick rows per first-phase item
     int32_t row_groups;  // first-phase items per z slice: ceil(By / rows)
+    int32_t row_lanes;   // lanes per brick row in the first phase (power of two)
     int32_t pad1[6];
     int32_t bounds[257];
+};
+
+// Grid-barrier state of the single-launch batched build, one word per
+// 128-byte line, zeroed before each launch.
+struct BatchSync {
+    uint32_t error;  // non-zero: a barrier wait gave up
+    uint32_t pad0[31];
+    uint32_t arrive;  // arrivals so far, over all barriers
+    uint32_t pad1[31];
+    uint32_t generation;  // barriers completed
+    uint32_t pad2[31];
+    uint32_t ticket[3][32];  // next item of each phase (one line each)
 };
 
 struct BrickArgs {
@@ -68,7 +81,6 @@ struct BrickArgs {
     void* bmax;
     int32_t* range_err;
     int nx, ny, nz, Bx, By, Bz, bytes, levels;
-    int vec_ok;     // 16-byte voxel-row loads allowed
     int store_vec;  // packed stores of 4 bricks allowed
 };
 
@@ -85,7 +97,7 @@ struct PlainArgs {
     const void* vol;
     uint8_t* dist;
     int nx, ny, nz, Bx, By, Bz, bytes, nwords, levels;
-    int vec_ok, store_vec;
+    int store_vec;
 };
 
 struct PomExactArgs {
@@ -93,7 +105,7 @@ struct PomExactArgs {
     uint8_t* pdms;
     int64_t G;
     int nx, ny, nz, Bx, By, Bz, bytes, n, levels;
-    int vec_ok, store_vec;
+    int store_vec;
 };
 
 hipError_t launch_bricks(const BrickArgs& a, hipStream_t s);
@@ -102,10 +114,13 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
 hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s);
-// Uploads `count` descriptors into d_vols, then runs the three grouped build
-// launches over totals[ph] items each; a y/z item covers 64*lines_mult lines.
+// Uploads `count` descriptors into d_vols and zeroes d_sync, then runs the
+// build over totals[ph] items per phase: three grouped launches, or with
+// `single` one cooperative launch with grid barriers between the phases; a
+// y/z item covers 64*lines_mult lines.
 hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
-                              const int64_t totals[3], int lines_mult, hipStream_t s);
+                              BatchSync* d_sync, const int64_t totals[3], int lines_mult,
+                              int single, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
 hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
                           int vec, hipStream_t s);

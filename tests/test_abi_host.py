@@ -181,3 +181,5 @@ def test_batch_build_validation(lib):
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_cfg, NULL) == L.PDM_E_INVAL
     bad_rows = ctypes.pointer(L.BatchConfig(257, 1, 0, 0))
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_rows, NULL) == L.PDM_E_INVAL
+    bad_mode = ctypes.pointer(L.BatchConfig(0, 1, 0, 2))
+    assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_mode, NULL) == L.PDM_E_INVAL

@@ -316,12 +316,17 @@ def test_batch_tf_update_matches_oracle(pdm, orc):
 # ------------------------------------------------------ batched build
 @pytest.mark.parametrize("config", [None, dict(rows_per_item=1, lines_mult=4, largest_first=1),
                                     dict(rows_per_item=7, lines_mult=1),
-                                    dict(rows_per_item=256, lines_mult=16, largest_first=1)],
-                         ids=["default", "one-row-long-chunks", "seven-rows", "whole-slices"])
+                                    dict(rows_per_item=256, lines_mult=16, largest_first=1),
+                                    dict(single_launch=1),
+                                    dict(single_launch=1, rows_per_item=1, lines_mult=2,
+                                         largest_first=1)],
+                         ids=["default", "one-row-long-chunks", "seven-rows", "whole-slices",
+                              "single-launch", "single-launch-one-row"])
 def test_batch_build_matches_single_volume_and_oracle(pdm, orc, config):
-    """Three grouped launches build bricks and PDMs of volumes of mixed
-    dtypes, ragged sizes and partition counts, including grid axes of 1 and
-    of the 256-brick maximum; each against the oracle."""
+    """Bricks and PDMs of volumes of mixed dtypes, ragged sizes and partition
+    counts, including grid axes of 1 and of the 256-brick maximum, built by
+    the three grouped launches or by the single cooperative launch; each
+    against the oracle and the single-volume calls."""
     import torch
     specs = [((37, 29, 45), np.uint8, 256, 16), ((20, 24, 64), np.uint16, 4096, 32),
              ((9, 14, 30), np.uint8, 256, 64), ((64, 64, 64), np.uint8, 256, 8),
@@ -339,6 +344,7 @@ def test_batch_build_matches_single_volume_and_oracle(pdm, orc, config):
     say(f"[case] batch build of {len(items)} volumes, config {config}")
     pdm.batch_build(items, ws, config)
     torch.cuda.synchronize()
+    assert pdm.batch_error(ws) == 0
     for k, (vol, v, bounds, L) in enumerate(vols):
         bmin, bmax = orc.bricks(vol)
         np.testing.assert_array_equal(pdm.from_device(v.bmin, vol.dtype), bmin, err_msg=f"bmin {k}")
