@@ -19,7 +19,7 @@ oracle timed on a slab of the same volume (see `cpu_baseline()`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
                        [--no-cpu-baseline] [--calib-copy-mib M]
-                       [--workload tube_tree|batched]
+                       [--workload tube_tree|batched|served|sweep]
 
 --workload served: a Poisson stream of TF changes (2k/s) over 24 resident
 volumes (22 of the batched recipe and two 1024x1024x795 tube trees) served
@@ -27,9 +27,14 @@ with continuous batching; p50/p99 latency and updates/s, beside the same
 schedule through a serial full-recompute queue (service times measured per
 volume on the GPU).
 
+--workload sweep: partition counts 16..256, uniform and with a partition of
+its own for rho_min, on the CT-like u16 volume, the tube tree and an
+832x832x494 stag-beetle-shaped u8 volume (see run_sweep).
+
 --workload batched: 48 volumes of uneven sizes (96-640 per axis, half u8 and
-half 12-bit u16, 16/32/64 partitions).  Times the one-launch persistent build
-(launch shape from the autotuner) against a per-volume launch loop, and the
+half 12-bit u16, 16/32/64 partitions).  Times the batched build (grouped or
+single launch, chosen with the rest of the launch shape by the autotuner)
+against a per-volume launch loop, and the
 one-launch TF update of all 48 volumes (a different TF each) against a
 per-volume loop; checks that both ways give identical bytes.
 """
@@ -143,7 +148,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
-    ap.add_argument("--workload", default="tube_tree", choices=("tube_tree", "batched", "served"))
+    ap.add_argument("--workload", default="tube_tree",
+                    choices=("tube_tree", "batched", "served", "sweep"))
+    ap.add_argument("--sweep-tfs", type=int, default=40)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
@@ -164,6 +171,9 @@ def main():
         return
     if args.workload == "served":
         run_served(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
     cfg = W.config_info("c3")
     L, n = cfg["levels"], cfg["n"]
@@ -512,6 +522,111 @@ def run_served(args):
         "serial_single_update": serial_queue(sched, upd_s),
         "service_ms_mean": {"full_recompute": round(1e3 * float(np.mean(list(full_s.values()))), 4),
                             "tf_update": round(1e3 * float(np.mean(list(upd_s.values()))), 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """Partition sweep: n = 16..256 with uniform partitions and with a
+    partition of its own for the minimum intensity (Sec. 3.1 and Fig. 4), on
+    the CT-like 512x512x460 u16, the 1024x1024x795 tube tree and an
+    832x832x494 stag-beetle-shaped u8 volume whose background sits at
+    rho_min.  Per point: init time (bricks + PDMs), PDM bytes n*G, TF-update
+    and full-recompute times over the same TFs, and how much of the plain
+    method's distance D the update keeps (D' == D fraction, mean D' / mean
+    D; D' <= D always)."""
+    import torch
+    import paper_2407_21552_amd as pdm
+    import workloads as W
+
+    stream = torch.cuda.current_stream()
+    T = args.sweep_tfs
+    cases = [
+        ("ct_like_512x512x460_u16", lambda: W.make_volume("c2"), 4096, lambda: W.make_tfs("c2", T)),
+        ("tube_tree_1024x1024x795_u8", lambda: W.make_volume("c3"), 256, lambda: W.make_tfs("c3", T)),
+        ("stag_beetle_832x832x494_u8", lambda: W.stag_beetle_u8(), 256, lambda: W.stag_tfs(T)),
+    ]
+    ns = [16, 32, 64, 128, 256]
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    points = []
+    upd_bytes_total, upd_ms_total = 0.0, 0.0
+    for name, make, L, make_tfs in cases:
+        log(f"sweep: generating {name} ...")
+        host = make()
+        rho_min = int(host.min())
+        dvol = pdm.to_device(host)
+        alphas = make_tfs()
+        del host
+        for kind in ("uniform", "rho_min"):
+            for n in ns:
+                bounds = (W.uniform_bounds(L, n) if kind == "uniform"
+                          else W.rhomin_bounds(L, n, rho_min))
+                v = pdm.Volume(dvol, L, bounds)
+                v.build(stream)
+                builds = []
+                for _ in range(3):
+                    a = ev()
+                    v.build(stream)
+                    b = ev()
+                    b.synchronize()
+                    builds.append(a.elapsed_time(b))
+                d_full = torch.empty_like(v.dist)
+                upd, full, sizes, eq, ratio = [], [], [], [], []
+                for k, alpha in enumerate(alphas):
+                    e0 = ev()
+                    mask = v.update_tf(alpha, stream=stream)
+                    e1 = ev()
+                    v.full_recompute(alpha, out=d_full, stream=stream)
+                    e2 = ev()
+                    e2.synchronize()
+                    upd.append(e0.elapsed_time(e1))
+                    full.append(e1.elapsed_time(e2))
+                    act = pdm.mask_to_list(mask, v.n)
+                    sizes.append(len(act))
+                    assert bool((v.dist <= d_full).all().item()), "D' > D"
+                    if k < 3:
+                        # Eq. 1 against a plain PyTorch min over the active maps
+                        want = (v.pdms[act].amin(0) if act else
+                                torch.full_like(v.dist, 255))
+                        assert torch.equal(v.dist, want), "D' differs from the min over S"
+                    eq.append(float((v.dist == d_full).float().mean().item()))
+                    df = float(d_full.float().mean().item())
+                    ratio.append(float(v.dist.float().mean().item()) / df if df > 0 else 1.0)
+                ub = sum((k + 1) * v.G for k in sizes)
+                upd_bytes_total += ub
+                upd_ms_total += sum(upd)
+                points.append({
+                    "volume": name, "partition": kind, "n": n, "rho_min": rho_min,
+                    "init_ms": round(float(np.median(builds)), 3), "pdm_bytes": n * v.G,
+                    "update_p50_ms": round(pct(upd, 50), 4), "update_mean_ms": round(float(np.mean(upd)), 4),
+                    "update_GBps": round(ub / (sum(upd) * 1e-3) / 1e9, 1),
+                    "mean_active": round(float(np.mean(sizes)), 2),
+                    "full_mean_ms": round(float(np.mean(full)), 4),
+                    "speedup_mean": round(float(np.mean(full)) / float(np.mean(upd)), 2),
+                    "d_equal_frac": round(float(np.mean(eq)), 4),
+                    "d_mean_ratio": round(float(np.mean(ratio)), 4)})
+                log(json.dumps(points[-1]))
+                del v, d_full
+                torch.cuda.empty_cache()
+        del dvol
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "partition sweep: init ms, PDM bytes, TF-update ms/GB/s and D' retention vs n, "
+                  "uniform vs rho_min partition",
+        "value": round(upd_bytes_total / (upd_ms_total * 1e-3) / 1e9, 1),
+        "unit": "GB/s (TF update, all points)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u8",
+        "data": "synthetic (CT-like u16, tube tree u8, stag-beetle-shaped u8 with background at rho_min)",
+        "config": {"workload": f"n in {ns}, uniform and rho_min partitions, {T} TFs per point, bricks 4^3",
+                   "tfs": T},
+        "points": points,
     }
     print(json.dumps(out), flush=True)
 

@@ -135,6 +135,21 @@ def test_rhomin_partition(pdm, orc):
     run_all(pdm, orc, vol, 256, bounds, tfs(256, 8, 5), "rho_min partition")
 
 
+@pytest.mark.parametrize("n", [16, 128, 256])
+@pytest.mark.parametrize("kind", ["uniform", "rho_min"])
+def test_partition_sweep_stag_beetle(pdm, orc, n, kind):
+    """The partition sweep's corners on a small stag-beetle-shaped volume
+    (background exactly at rho_min = 0): n from 16 to one partition per
+    level, uniform or with the rho_min partition [0, 0]."""
+    vol = W.stag_beetle_u8((62, 104, 104))
+    bounds = W.uniform_bounds(256, n) if kind == "uniform" else W.rhomin_bounds(256, n, 0)
+    alphas = tfs(256, 4, n)
+    low = np.zeros(256, np.float32)
+    low[1:40] = 0.5      # low intensities without rho_min itself
+    alphas.append(low)
+    run_all(pdm, orc, vol, 256, bounds, alphas, f"stag sweep {kind} n={n}")
+
+
 def test_deterministic_and_no_out_of_bounds_writes(pdm, orc):
     """Outputs written into the middle of guarded buffers: guard bytes stay
     untouched and two runs give identical bytes."""

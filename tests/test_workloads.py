@@ -49,3 +49,25 @@ def test_uniform_and_rhomin_bounds():
     r = W.rhomin_bounds(256, 32, 0)
     assert r[0] == 0 and r[1] == 1 and r[-1] == 256 and (np.diff(r) > 0).all()
     assert len(r) == 33
+
+
+def test_stag_beetle_volume():
+    a = W.stag_beetle_u8((62, 104, 104))
+    b = W.stag_beetle_u8((62, 104, 104))
+    assert a.dtype == np.uint8 and a.shape == (62, 104, 104)
+    assert a.tobytes() == b.tobytes()
+    zero = a == 0
+    assert zero.mean() > 0.8                               # heavy rho_min mass
+    assert (a > 120).mean() > 0.005                        # bright shell, mandibles, legs
+    # the body is connected around the centre and the border is background
+    assert a[31, 52, 52] > 0 and a[:, :, 0].max() <= 24
+    assert W.stag_tfs(3)[0].shape == (256,)
+
+
+@pytest.mark.parametrize("L,n,rho", [(256, 16, 0), (256, 256, 0), (4096, 128, 7), (256, 2, 0)])
+def test_rhomin_bounds_tile_the_range(L, n, rho):
+    r = W.rhomin_bounds(L, n, rho)
+    assert len(r) == n + 1 and r[0] == 0 and r[1] == rho + 1 and r[-1] == L
+    assert (np.diff(r) > 0).all()
+    sizes = np.diff(r[1:])
+    assert sizes.max() - sizes.min() <= 1                  # the rest split evenly

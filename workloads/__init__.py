@@ -37,7 +37,7 @@ def _chunk_map(fn, nz: int, seed: int, salt: int):
 __all__ = [
     "CONFIGS", "ellipsoids_u8", "ct_like_u16", "tube_tree_u8", "make_volume",
     "trapezoid_tf", "make_tfs", "uniform_bounds", "rhomin_bounds", "config_info",
-    "batch_specs", "batch_volume", "poisson_requests",
+    "batch_specs", "batch_volume", "poisson_requests", "stag_beetle_u8", "STAG", "stag_tfs",
 ]
 
 # name -> (shape (nz,ny,nx), dtype, levels L, partitions n, volume seed,
@@ -214,6 +214,80 @@ def tube_tree_u8(shape=(795, 1024, 1024), seed=3, tubes=40, length=(80, 400), ra
         out[z0:z1] = np.clip(np.rint(sl), 0, 255).astype(np.uint8)
 
     _chunk_map(fill, nz, seed, 1)
+    return out
+
+
+def stag_beetle_u8(shape=(494, 832, 832), seed=7, sigma=6.0, speckle=2e-4) -> np.ndarray:
+    """A stag-beetle-shaped uint8 volume whose background is exactly the
+    minimum intensity 0, so most voxels sit at rho_min (the case the rho_min
+    partition targets).  The beetle lies along y: head, thorax and abdomen
+    are ellipsoids with a bright shell (170..230) around a darker interior
+    (40..90); two curved mandibles (190..240), six two-segment legs
+    (150..210) and two antennae are capsules.  Object voxels get N(0, sigma)
+    noise and are clipped to [1, 255]; background voxels stay 0 except a
+    sparse speckle (probability `speckle`, values 1..24)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    base = np.zeros(shape, np.uint8)
+    cz, cx = nz / 2.0, nx / 2.0
+    parts = [(0.64, (0.30, 0.22, 0.21)), (0.42, (0.24, 0.10, 0.18)), (0.30, (0.19, 0.07, 0.14))]
+    for fy, (sz, sy, sx) in parts:
+        c = (cz, fy * ny, cx)
+        semi = (sz * nz, sy * ny, sx * nx)
+        _ellipsoid_fill(base, c, semi, int(rng.integers(170, 231)))
+        _ellipsoid_fill(base, c, tuple(0.85 * a for a in semi), int(rng.integers(40, 91)))
+    head_y = (0.30 - 0.07) * ny
+    for side in (-1.0, 1.0):
+        # mandible: three segments curving outwards then inwards
+        p = np.array([cz, head_y + 0.02 * ny, cx + side * 0.06 * nx])
+        val = int(rng.integers(190, 241))
+        for dy, dx in ((-0.08, 0.05), (-0.07, 0.02), (-0.05, -0.04)):
+            q = p + np.array([rng.uniform(-0.02, 0.02) * nz, dy * ny, side * dx * nx])
+            _capsule_fill(base, p, q, rng.uniform(0.008, 0.012) * nx, val)
+            p = q
+        # antenna
+        a0 = np.array([cz - 0.05 * nz, head_y + 0.03 * ny, cx + side * 0.08 * nx])
+        a1 = a0 + np.array([-0.05 * nz, -0.10 * ny, side * 0.12 * nx])
+        _capsule_fill(base, a0, a1, 0.003 * nx + 1.0, int(rng.integers(150, 211)))
+        for fy in (0.40, 0.52, 0.66):
+            # leg: from the body's side outwards and down, then back
+            l0 = np.array([cz + 0.05 * nz, fy * ny, cx + side * 0.12 * nx])
+            l1 = l0 + np.array([0.15 * nz, rng.uniform(-0.06, 0.06) * ny, side * 0.18 * nx])
+            l2 = l1 + np.array([0.12 * nz, rng.uniform(-0.08, 0.08) * ny, side * 0.08 * nx])
+            val = int(rng.integers(150, 211))
+            rad = rng.uniform(0.004, 0.007) * nx + 1.0
+            _capsule_fill(base, l0, np.clip(l1, 0, np.array(shape) - 1), rad, val)
+            _capsule_fill(base, np.clip(l1, 0, np.array(shape) - 1), np.clip(l2, 0, np.array(shape) - 1),
+                          0.8 * rad, val)
+    out = np.empty(shape, np.uint8)
+
+    def fill(z0, z1, r):
+        b = base[z0:z1]
+        obj = b > 0
+        noisy = np.clip(np.rint(b.astype(np.float32)
+                                + np.float32(sigma) * r.standard_normal(size=b.shape, dtype=np.float32)),
+                        1, 255).astype(np.uint8)
+        sl = np.where(obj, noisy, np.uint8(0))
+        spk = (~obj) & (r.random(size=b.shape, dtype=np.float32) < speckle)
+        sl[spk] = r.integers(1, 25, size=int(spk.sum()), dtype=np.uint8)
+        out[z0:z1] = sl
+
+    _chunk_map(fill, nz, seed, 3)
+    return out
+
+
+STAG = dict(shape=(494, 832, 832), dtype=np.uint8, levels=256, seed=7, rho_min=0,
+            tfs=50, ramps=(1, 3), tf_seed=7000)
+
+
+def stag_tfs(count: int = 50):
+    """TFs for the stag-beetle volume: TF k from seed tf_seed + k, U{ramps}
+    trapezoids."""
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng(STAG["tf_seed"] + k)
+        r = int(rng.integers(STAG["ramps"][0], STAG["ramps"][1] + 1))
+        out.append(trapezoid_tf(STAG["levels"], r, rng))
     return out
 
 
