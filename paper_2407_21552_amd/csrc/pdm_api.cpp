@@ -71,6 +71,14 @@ pdm_status plain_args(const pdm_volume* v, const void* d_volume, const float* h_
     memset(bits, 0, sizeof(*bits));
     for (int32_t i = 0; i < v->levels; ++i)
         if (h_alpha[i] != 0.0f) bits->w[i >> 5] |= 1u << (i & 31);
+    // prefix counts of set bits per word: any set bit in [lo, hi] is O(1)
+    const int32_t nwords = (v->levels + 31) / 32;
+    uint32_t acc = 0;
+    for (int32_t i = 0; i < nwords; ++i) {
+        bits->pre[i] = (uint16_t)acc;
+        acc += (uint32_t)__builtin_popcount(bits->w[i]);
+    }
+    bits->pre[nwords] = (uint16_t)acc;
     a->vol = d_volume;
     a->dist = d_dist;
     a->nx = v->nx;

@@ -82,6 +82,19 @@ __device__ __forceinline__ uint4 load16(const PDM_GLB void* p) {
     return w;
 }
 
+// 16 bytes from any byte address, non-temporal: voxels are streamed once per
+// pass and the volume does not fit in the caches, so they should not evict
+// what does.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef u32x4 u32x4_u __attribute__((aligned(1)));
+
+__device__ __forceinline__ u32x4 load16_nt(const void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4_u*>(p));
+}
+__device__ __forceinline__ u32x4 load16_nt(const PDM_GLB void* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const PDM_GLB u32x4_u*>(p));
+}
+
 template <typename T>
 struct QuadMinMax {
     uint32_t mn[4], mx[4];
@@ -94,7 +107,69 @@ __device__ __forceinline__ QuadMinMax<T> quad_minmax(VP __restrict__ vol, int nx
     const int x0 = 16 * q;
     const int z0 = 4 * bz, y0 = 4 * by;
     const int zn = min(4, nz - z0), yn = min(4, ny - y0);
-    if (x0 + 16 <= nx) {
+    if (zn == 4 && yn == 4 && x0 + 16 <= nx) {
+        // a full quad: every row load is issued before the first use
+        const int64_t base = ((int64_t)z0 * ny + y0) * nx + x0;
+        if constexpr (sizeof(T) == 1) {
+            u32x4 w[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                w[i] = load16_nt(vol + base + ((int64_t)(i >> 2) * ny + (i & 3)) * nx);
+            uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t ws[4] = {w[i].x, w[i].y, w[i].z, w[i].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
+                    mnE[k] = pk_min16(mnE[k], e);
+                    mnO[k] = pk_min16(mnO[k], o);
+                    mxE[k] = pk_max16(mxE[k], e);
+                    mxO[k] = pk_max16(mxO[k], o);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a = pk_min16(mnE[k], mnO[k]);
+                const uint32_t b = pk_max16(mxE[k], mxO[k]);
+                r.mn[k] = umin(lo16(a), hi16(a));
+                r.mx[k] = umax(lo16(b), hi16(b));
+            }
+        } else {
+            // u16: 32 bytes per row; two rounds of 8 rows (16 loads each)
+            uint32_t mn[4], mx[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                u32x4 w[16];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t off = base + ((int64_t)(2 * h + (i >> 2)) * ny + (i & 3)) * nx;
+                    w[2 * i] = load16_nt(vol + off);
+                    w[2 * i + 1] = load16_nt(vol + off + 8);
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t ws[8] = {w[2 * i].x, w[2 * i].y, w[2 * i].z, w[2 * i].w,
+                                            w[2 * i + 1].x, w[2 * i + 1].y, w[2 * i + 1].z, w[2 * i + 1].w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
+                        mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
+                r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
+            }
+        }
+    } else if (x0 + 16 <= nx) {
+        // partial in z or y: row by row
         if constexpr (sizeof(T) == 1) {
             // even/odd byte lanes held as packed u16 pairs, one pair per brick
             uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
@@ -419,33 +494,30 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
     __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
     __shared__ uint16_t s_pre[PDM_ALPHA_WORDS + 1];
     __shared__ uint8_t s_nib[4][kMaxSegs][kWave];
-    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int i = 0; i < nwords; ++i) {
-            s_pre[i] = (uint16_t)acc;
-            acc += __popc(s_words[i]);
-        }
-        s_pre[nwords] = (uint16_t)acc;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
-    if (row >= rows) return;  // wave-uniform, after the last barrier
-    const int by = (int)(row % By), bz = (int)(row / By);
+    const bool live = row < rows;  // wave-uniform
+    const int by = live ? (int)(row % By) : 0, bz = live ? (int)(row / By) : 0;
+    // the first segment's voxels are requested before the bitmap set-up, so
+    // the loads are in flight while the block fills LDS
+    QuadMinMax<T> r0;
+    if (live && 4 * lane < Bx) r0 = quad_minmax<T>(vol, nx, ny, nz, lane, by, bz);
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
+    for (int i = threadIdx.x; i <= nwords; i += blockDim.x) s_pre[i] = bits.pre[i];
+    __syncthreads();
+    if (!live) return;  // after the only barrier
     const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
     const int64_t rbase = row * Bx;
+    // voxels >= levels break the precondition; clamping keeps the bitmap
+    // lookups inside the table
+    const uint32_t top = (uint32_t)levels - 1u;
     for (int s = 0; s < nseg; ++s) {
         const int q = s * kWave + lane;  // quad index within the row
         uint32_t o = 0;
         if (4 * q < Bx) {
-            const QuadMinMax<T> r = quad_minmax<T>(vol, nx, ny, nz, q, by, bz);
+            const QuadMinMax<T> r = s == 0 ? r0 : quad_minmax<T>(vol, nx, ny, nz, q, by, bz);
             const int nb = min(4, Bx - 4 * q);
-            // voxels >= levels break the precondition; clamping keeps the
-            // bitmap lookups inside the table
-            const uint32_t top = (uint32_t)levels - 1u;
             for (int k = 0; k < 4; ++k)
                 if (k < nb && any_bit(s_words, s_pre, umin(r.mn[k], top), umin(r.mx[k], top)))
                     o |= 1u << k;
@@ -849,8 +921,6 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
 // VEC = 4 and VEC = 1 serve sizes or pointers that are not 16-byte aligned.
 // An empty list writes 255.
 // ---------------------------------------------------------------------------
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ u32x4 load_nt16(const uint8_t* p) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
 }

@@ -26,6 +26,7 @@ struct ActiveList {
 // Bit i set when alpha[i] != 0, passed by value.
 struct AlphaBits {
     uint32_t w[PDM_ALPHA_WORDS];
+    uint16_t pre[PDM_ALPHA_WORDS + 2];  // pre[i] = set bits in w[0..i-1] (i <= nwords)
 };
 
 // One volume of a batched TF update (72 bytes), passed by value.
