@@ -89,6 +89,40 @@ def load_traffic():
     return rec
 
 
+def range_table_leg(pdm, torch, stream, v, desc, bounds, alphas, masks, n, G, max_level):
+    """Build the range table over the PDMs and run every TF through it (HIP
+    events on the library's stream).  Checks D' against the plain update on
+    every TF.  Bytes per update: (maps read + 1) * G."""
+    maps = pdm.range_table_maps(n, max_level)
+    table = torch.empty((maps, G), dtype=torch.uint8, device="cuda")
+    ref = torch.empty_like(v.dist)
+    out = torch.empty_like(v.dist)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    pdm.build_range_table(desc, v.pdms, n, max_level, table, stream)
+    b0, b1 = ev(), ev()
+    b0.record(stream)
+    pdm.build_range_table(desc, v.pdms, n, max_level, table, stream)
+    b1.record(stream)
+    times, covers = [], []
+    for a, m in zip(alphas, masks):
+        pdm.tf_update(desc, v.pdms, bounds, a, ref, stream)
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        pdm.tf_update_ranges(desc, v.pdms, table, bounds, max_level, a, out, stream)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+        covers.append(len(pdm.range_cover(n, max_level, m)))
+        assert torch.equal(out, ref), "range-table D' differs from the plain update"
+    gbytes = sum((c + 1) * G for c in covers)
+    return {"p50_ms": round(pct(times, 50), 4), "p99_ms": round(pct(times, 99), 4),
+            "mean_ms": round(float(np.mean(times)), 4), "mean_maps_read": round(float(np.mean(covers)), 2),
+            "GBps": round(gbytes / (sum(times) * 1e-3) / 1e9, 1),
+            "table_maps": maps, "table_bytes": maps * G, "max_level": max_level,
+            "table_build_ms": round(b0.elapsed_time(b1), 3),
+            "identical_to_eq1_update": True}
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
@@ -151,6 +185,9 @@ def main():
     ap.add_argument("--workload", default="tube_tree",
                     choices=("tube_tree", "batched", "served", "sweep"))
     ap.add_argument("--sweep-tfs", type=int, default=40)
+    ap.add_argument("--range-level", type=int, default=8,
+                    help="top level of the range table (the TF updates through it are reported "
+                         "beside the plain update)")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
@@ -255,6 +292,11 @@ def main():
     # parity spot check on the last TF: D' <= D everywhere (Sec. 3.1)
     assert bool((v.dist <= d_full).all().item()), "D' > D"
 
+    # the same TFs through the range table (outside the step: an option of
+    # the update, not one of the method's steps)
+    log("range table: build + the same TFs through it ...")
+    rt = range_table_leg(pdm, torch, stream, v, desc, bounds, alphas, masks, n, G, args.range_level)
+
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
@@ -326,6 +368,9 @@ def main():
                              f"V*s + G = {plain_bytes} B per launch (volume read + x-distance write)"),
         "roofline_tf_update": roofline("k_combine", upd_gbps,
                                        "(|S|+1)*G B per launch, summed over the TFs"),
+        "tf_update_range_table": {
+            **rt, "speedup_vs_eq1_update_p50": round(pct(upd_ms, 50) / rt["p50_ms"], 2),
+            "speedup_vs_full_p50": round(pct(full_ms, 50) / rt["p50_ms"], 2)},
         "paper_context": PAPER_CONTEXT,
         "kernel_source_sha256_16": kernel_hash(),
     }

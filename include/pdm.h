@@ -122,6 +122,48 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
                          int32_t n, const float* h_alpha, uint8_t* d_dist, uint64_t* h_active,
                          hipStream_t stream);
 
+/* Range tables: a way to run step 2 of the TF update (Eq. 1) that reads
+ * fewer maps.  The distance map of a union of partitions is the element-wise
+ * min of their maps (the distance to a union is the min of the distances;
+ * Sec. 3.1), so the maps of runs of 2^k consecutive partitions can be built
+ * once and reused.  Level k (1 <= k <= K, K = min(max_level, floor(log2 n)))
+ * holds the n - 2^k + 1 maps T_k[p] = min(PDM_p, ..., PDM_{p+2^k-1}),
+ * p = 0 .. n-2^k, each G bytes like the PDMs, level after level in one
+ * buffer.  A TF whose S is R runs of consecutive partitions is then combined
+ * from at most 2R maps (runs longer than 2^(K+1) take more) instead of |S|;
+ * D' is identical.  Memory: pdm_range_table_maps(n, max_level) * G bytes
+ * (n = 64, max_level 6: 264 maps).
+ *
+ * pdm_range_table_maps: maps in the table; 0 when K = 0; -1 for n outside
+ * [1, 256] or max_level < 0.  Host only. */
+int64_t pdm_range_table_maps(int32_t n, int32_t max_level);
+
+/* Builds levels 1..K of the table from d_pdms (n*G bytes) into d_table
+ * (pdm_range_table_maps(n, max_level) * G bytes, caller-owned; may be null
+ * when K = 0).  One launch per level; level k reads two maps of level k-1
+ * per map written. */
+pdm_status pdm_build_range_table(const pdm_volume* v, const uint8_t* d_pdms, int32_t n,
+                                 int32_t max_level, uint8_t* d_table, hipStream_t stream);
+
+/* The maps combined for the active set h_active (4 words, as from
+ * pdm_active_set): *h_count indices into h_maps (room for 256), index i < n
+ * is PDM i and i >= n is table map i - n.  Every maximal run [a, b] of S
+ * takes PDM a when a = b, else the one or two level-floor(log2(b-a+1)) maps
+ * covering it (past level K: level-K maps every 2^K partitions and one
+ * ending at b).  The union of the covered partitions is exactly S.  Host
+ * only. */
+pdm_status pdm_range_cover(int32_t n, int32_t max_level, const uint64_t* h_active,
+                           int32_t* h_maps, int32_t* h_count);
+
+/* pdm_tf_update reading the cover's maps instead of every PDM of S: the same
+ * D' and S mask.  d_table: built by pdm_build_range_table with the same n and
+ * max_level (null allowed when K = 0). */
+pdm_status pdm_tf_update_ranges(const pdm_volume* v, const uint8_t* d_pdms, const uint8_t* d_table,
+                                const int32_t* h_bounds, int32_t n, int32_t max_level,
+                                const float* h_alpha, uint8_t* d_dist, uint64_t* h_active,
+                                hipStream_t stream);
+
+
 /* Plain method (Sec. 2 and Sec. 4.2): from the raw volume, the occupancy of
  * every brick under the TF (occupied when some intensity i in the brick's
  * [min, max] has h_alpha[i] != 0) and its clamped chessboard distance map D.

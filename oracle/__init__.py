@@ -194,6 +194,25 @@ def tf_update(pdm_stack, bounds, alpha, levels: int):
     return combine(pdm_stack, m), m
 
 
+def range_table(pdm_stack, max_level: int) -> np.ndarray:
+    """The range-table maps, level after level (k = 1 .. K, K = min(max_level,
+    floor(log2 n))): map T_k[p] is the element-wise min of PDMs p .. p+2^k-1,
+    the distance map of the union of those partitions (the distance to a
+    union is the min of the distances; Sec. 3.1).  Written from that
+    definition, one np.min per map."""
+    n = pdm_stack.shape[0]
+    out = []
+    k = 1
+    while k <= max_level and (1 << k) <= n:
+        w = 1 << k
+        for p in range(n - w + 1):
+            out.append(pdm_stack[p:p + w].min(axis=0))
+        k += 1
+    if not out:
+        return np.zeros((0,) + pdm_stack.shape[1:], np.uint8)
+    return np.stack(out)
+
+
 def plain_occ_range(bmin, bmax, alpha, levels: int) -> np.ndarray:
     bmin = np.ascontiguousarray(bmin, np.uint16)
     bmax = np.ascontiguousarray(bmax, np.uint16)

@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, PreparedVolume,
                    active_set, batch_build, batch_error, batch_tf_update, batch_tf_update_prepared,
-                   batch_workspace_bytes, build_bricks,
+                   batch_workspace_bytes, build_bricks, build_range_table, range_cover,
+                   range_table_maps, tf_update_ranges,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
                    full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
@@ -26,7 +27,8 @@ from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, Prepare
 
 __all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build", "batch_error",
            "batch_tf_update", "batch_tf_update_prepared", "batch_workspace_bytes", "BATCH_MAX",
-           "build_bricks", "build_partitions",
+           "build_bricks", "build_partitions", "build_range_table", "range_cover",
+           "range_table_maps", "tf_update_ranges",
            "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
            "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
            "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",
@@ -94,6 +96,21 @@ class Volume:
             build_partitions_exact(self.desc, self.volume, self.bounds, self.pdms, stream)
         else:
             build_partitions(self.desc, self.bmin, self.bmax, self.bounds, self.pdms, stream)
+
+    def build_range_table(self, max_level: int = 8, stream=None) -> None:
+        """Allocate and build the range table over this volume's PDMs (call
+        after build()); update_tf_ranges then reads the covering maps."""
+        import torch
+        self.range_level = int(max_level)
+        maps = range_table_maps(self.n, self.range_level)
+        self.table = (torch.empty((maps, self.bz, self.by, self.bx), dtype=torch.uint8,
+                                  device=self.pdms.device) if maps > 0 else None)
+        build_range_table(self.desc, self.pdms, self.n, self.range_level, self.table, stream)
+
+    def update_tf_ranges(self, alpha, out=None, stream=None) -> np.ndarray:
+        """update_tf through the range table (same D' and S mask)."""
+        return tf_update_ranges(self.desc, self.pdms, self.table, self.bounds, self.range_level,
+                                alpha, self.dist if out is None else out, stream)
 
     @property
     def prepared(self) -> PreparedVolume:

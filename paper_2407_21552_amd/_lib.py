@@ -97,8 +97,14 @@ def lib() -> ctypes.CDLL:
                      "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
                      "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
                      "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
-                     "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build"):
+                     "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build",
+                     "pdm_build_range_table", "pdm_range_cover", "pdm_tf_update_ranges"):
             getattr(L, name).restype = st
+        L.pdm_range_table_maps.argtypes = [i32, i32]
+        L.pdm_range_table_maps.restype = ctypes.c_int64
+        L.pdm_build_range_table.argtypes = [V, P, i32, i32, P, P]
+        L.pdm_range_cover.argtypes = [i32, i32, P, P, P]
+        L.pdm_tf_update_ranges.argtypes = [V, P, P, P, i32, i32, P, P, P, P]
         L.pdm_status_string.argtypes = [st]
         L.pdm_status_string.restype = ctypes.c_char_p
         L.pdm_version.restype = ctypes.c_char_p
@@ -250,6 +256,55 @@ def tf_update(desc, pdms, bounds, alpha, dist, stream=None) -> np.ndarray:
     _check(lib().pdm_tf_update(ctypes.byref(desc), _dev_ptr(pdms, n * G, "pdms"), _np_ptr(b), n,
                                _np_ptr(a), _dev_ptr(dist, G, "dist"), _np_ptr(m), _stream(stream)),
            "pdm_tf_update")
+    return m
+
+
+# ------------------------------------------------------------- range tables
+def range_table_maps(n: int, max_level: int) -> int:
+    """Maps in the range table of n partitions with levels 1..min(max_level,
+    floor(log2 n))."""
+    r = int(lib().pdm_range_table_maps(int(n), int(max_level)))
+    if r < 0:
+        raise ValueError(f"range table: n={n} must be in 1..256 and max_level={max_level} >= 0")
+    return r
+
+
+def build_range_table(desc, pdms, n: int, max_level: int, table, stream=None) -> None:
+    """Levels 1..K of the range table of `pdms` into `table` (a uint8 device
+    tensor of range_table_maps(n, max_level) * G bytes; None when that is 0)."""
+    G = grid_of(desc)[3]
+    maps = range_table_maps(n, max_level)
+    tp = _dev_ptr(table, maps * G, "table") if maps > 0 else ctypes.c_void_p(0)
+    _check(lib().pdm_build_range_table(ctypes.byref(desc), _dev_ptr(pdms, n * G, "pdms"), int(n),
+                                       int(max_level), tp, _stream(stream)),
+           "pdm_build_range_table")
+
+
+def range_cover(n: int, max_level: int, mask) -> list:
+    """Map indices combined for the S mask (i < n: PDM i, else table map i - n)."""
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint64))
+    if m.shape != (4,):
+        raise ValueError("mask must hold 4 uint64 words")
+    out = np.zeros(256, np.int32)
+    cnt = ctypes.c_int32(0)
+    _check(lib().pdm_range_cover(int(n), int(max_level), _np_ptr(m), _np_ptr(out), ctypes.byref(cnt)),
+           "pdm_range_cover")
+    return [int(x) for x in out[:cnt.value]]
+
+
+def tf_update_ranges(desc, pdms, table, bounds, max_level: int, alpha, dist, stream=None) -> np.ndarray:
+    """tf_update through the range table; returns the S mask."""
+    G = grid_of(desc)[3]
+    b = _bounds(bounds)
+    n = len(b) - 1
+    a = _alpha(alpha, desc.levels)
+    maps = range_table_maps(n, max_level)
+    tp = _dev_ptr(table, maps * G, "table") if maps > 0 else ctypes.c_void_p(0)
+    m = np.zeros(4, np.uint64)
+    _check(lib().pdm_tf_update_ranges(ctypes.byref(desc), _dev_ptr(pdms, n * G, "pdms"), tp,
+                                      _np_ptr(b), n, int(max_level), _np_ptr(a),
+                                      _dev_ptr(dist, G, "dist"), _np_ptr(m), _stream(stream)),
+           "pdm_tf_update_ranges")
     return m
 
 

@@ -11,7 +11,7 @@
 
 namespace {
 
-using pdm::ActiveList;
+using pdm::MapList;
 using pdm::AlphaBits;
 using pdm::Bounds;
 
@@ -58,6 +58,13 @@ void active_mask(const int32_t* b, int32_t n, const float* alpha, uint64_t mask[
 }
 
 pdm_status from_hip(hipError_t e) { return e == hipSuccess ? PDM_OK : PDM_E_DEVICE; }
+
+// Widest combine path the sizes and pointers allow.
+int combine_vec(int64_t G, const void* pdms, const void* out) {
+    if (G % 16 == 0 && aligned(pdms, 16) && aligned(out, 16)) return 16;
+    if (G % 4 == 0 && aligned(pdms, 4) && aligned(out, 4)) return 4;
+    return 1;
+}
 
 // Validation and kernel arguments shared by both readings of the plain
 // method: the non-zero opacity bitmap and the volume geometry.
@@ -196,16 +203,132 @@ pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32
     active_mask(h_bounds, n, h_alpha, mask);
     if (h_active != nullptr)
         for (int k = 0; k < 4; ++k) h_active[k] = mask[k];
-    ActiveList act;
-    memset(&act, 0, sizeof(act));
+    MapList maps;
+    memset(&maps, 0, sizeof(maps));
     for (int32_t p = 0; p < n; ++p)
-        if ((mask[p >> 6] >> (p & 63)) & 1ull) act.p[act.count++] = (uint8_t)p;
-    int vec = 1;
-    if (g.count % 16 == 0 && aligned(d_pdms, 16) && aligned(d_dist, 16))
-        vec = 16;
-    else if (g.count % 4 == 0 && aligned(d_pdms, 4) && aligned(d_dist, 4))
-        vec = 4;
-    return from_hip(pdm::launch_combine(d_pdms, g.count, act, d_dist, vec, stream));
+        if ((mask[p >> 6] >> (p & 63)) & 1ull) maps.src[maps.count++] = d_pdms + (int64_t)p * g.count;
+    return from_hip(pdm::launch_combine(maps, g.count, d_dist, combine_vec(g.count, d_pdms, d_dist),
+                                        stream));
+}
+
+// ------------------------------------------------------------ range tables
+namespace {
+
+int32_t range_levels(int32_t n, int32_t max_level) {
+    int32_t K = 0;
+    while (K < max_level && (2 << K) <= n) ++K;  // 2^(K+1) <= n
+    return K;
+}
+
+// First map of level k (1-based level) within the table.
+int64_t level_first(int32_t n, int32_t k) {
+    int64_t off = 0;
+    for (int32_t j = 1; j < k; ++j) off += n - (1 << j) + 1;
+    return off;
+}
+
+// Map indices (i < n: PDM i; i >= n: table map i - n) whose min is the min
+// over the partitions of `mask`: each maximal run [a, b] of length L takes
+// one PDM (L = 1), the one or two maps of level floor(log2 L) that cover it,
+// or, past the top level K, level-K maps every 2^K partitions plus one
+// ending at b.  Maps may overlap; min is idempotent.
+int32_t cover(int32_t n, int32_t K, const uint64_t* mask, int32_t* out) {
+    int32_t cnt = 0;
+    auto on = [&](int32_t p) { return ((mask[p >> 6] >> (p & 63)) & 1ull) != 0; };
+    auto tmap = [&](int32_t k, int32_t p) { return (int32_t)(n + level_first(n, k) + p); };
+    for (int32_t a = 0; a < n;) {
+        if (!on(a)) {
+            ++a;
+            continue;
+        }
+        int32_t b = a;
+        while (b + 1 < n && on(b + 1)) ++b;
+        const int32_t L = b - a + 1;
+        int32_t k = 0;
+        while ((2 << k) <= L) ++k;  // floor(log2 L)
+        if (k == 0 || K == 0) {
+            for (int32_t p = a; p <= b; ++p) out[cnt++] = p;
+        } else if (k <= K) {
+            out[cnt++] = tmap(k, a);
+            if (L != (1 << k)) out[cnt++] = tmap(k, b - (1 << k) + 1);
+        } else {
+            const int32_t w = 1 << K;
+            int32_t p = a;
+            for (; p + w - 1 < b; p += w) out[cnt++] = tmap(K, p);
+            out[cnt++] = tmap(K, b - w + 1);
+        }
+        a = b + 1;
+    }
+    return cnt;
+}
+
+}  // namespace
+
+int64_t pdm_range_table_maps(int32_t n, int32_t max_level) {
+    if (n < 1 || n > PDM_MAX_PARTITIONS || max_level < 0) return -1;
+    const int32_t K = range_levels(n, max_level);
+    return level_first(n, K + 1);
+}
+
+pdm_status pdm_range_cover(int32_t n, int32_t max_level, const uint64_t* h_active, int32_t* h_maps,
+                           int32_t* h_count) {
+    if (n < 1 || n > PDM_MAX_PARTITIONS || max_level < 0 || h_active == nullptr ||
+        h_maps == nullptr || h_count == nullptr)
+        return PDM_E_INVAL;
+    *h_count = cover(n, range_levels(n, max_level), h_active, h_maps);
+    return PDM_OK;
+}
+
+pdm_status pdm_build_range_table(const pdm_volume* v, const uint8_t* d_pdms, int32_t n,
+                                 int32_t max_level, uint8_t* d_table, hipStream_t stream) {
+    pdm_grid g;
+    const pdm_status st = check_volume(v, &g);
+    if (st != PDM_OK) return st;
+    if (d_pdms == nullptr || n < 1 || n > PDM_MAX_PARTITIONS || max_level < 0) return PDM_E_INVAL;
+    const int32_t K = range_levels(n, max_level);
+    if (K == 0) return PDM_OK;
+    if (d_table == nullptr) return PDM_E_INVAL;
+    const int64_t G = g.count;
+    const bool v16 = G % 16 == 0 && aligned(d_pdms, 16) && aligned(d_table, 16);
+    for (int32_t k = 1; k <= K; ++k) {
+        const uint8_t* src = k == 1 ? d_pdms : d_table + level_first(n, k - 1) * G;
+        uint8_t* dst = d_table + level_first(n, k) * G;
+        const int64_t count = n - (1 << k) + 1;
+        const hipError_t e = pdm::launch_range_level(src, 1 << (k - 1), dst, count, G, v16 ? 16 : 1,
+                                                     stream);
+        if (e != hipSuccess) return PDM_E_DEVICE;
+    }
+    return PDM_OK;
+}
+
+pdm_status pdm_tf_update_ranges(const pdm_volume* v, const uint8_t* d_pdms, const uint8_t* d_table,
+                                const int32_t* h_bounds, int32_t n, int32_t max_level,
+                                const float* h_alpha, uint8_t* d_dist, uint64_t* h_active,
+                                hipStream_t stream) {
+    pdm_grid g;
+    pdm_status st = check_volume(v, &g);
+    if (st != PDM_OK) return st;
+    if (d_pdms == nullptr || d_dist == nullptr || h_alpha == nullptr || max_level < 0)
+        return PDM_E_INVAL;
+    st = check_bounds(h_bounds, n, v->levels);
+    if (st != PDM_OK) return st;
+    const int32_t K = range_levels(n, max_level);
+    if (K > 0 && d_table == nullptr) return PDM_E_INVAL;
+    uint64_t mask[4];
+    active_mask(h_bounds, n, h_alpha, mask);
+    if (h_active != nullptr)
+        for (int k = 0; k < 4; ++k) h_active[k] = mask[k];
+    int32_t idx[PDM_MAX_PARTITIONS];
+    const int32_t cnt = cover(n, K, mask, idx);
+    MapList maps;
+    memset(&maps, 0, sizeof(maps));
+    maps.count = cnt;
+    for (int32_t j = 0; j < cnt; ++j)
+        maps.src[j] = idx[j] < n ? d_pdms + (int64_t)idx[j] * g.count
+                                 : d_table + (int64_t)(idx[j] - n) * g.count;
+    int vec = combine_vec(g.count, d_pdms, d_dist);
+    if (K > 0 && vec > 1 && !aligned(d_table, vec)) vec = 1;
+    return from_hip(pdm::launch_combine(maps, g.count, d_dist, vec, stream));
 }
 
 pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,

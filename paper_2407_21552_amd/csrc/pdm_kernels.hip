@@ -912,7 +912,8 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// k_combine: D'[c] = min over the listed partitions of pdms[p*G + c].
+// k_combine: D'[c] = min over the listed maps of map[c] (the active
+// partitions' PDMs, or range-table maps covering them).
 // VEC = 16: each lane owns two 16-byte vectors, `nthr` vectors apart so that
 // every load instruction of a wave covers 1 KiB of one stream; partitions are
 // taken two at a time, so four 16-byte non-temporal loads are in flight per
@@ -937,10 +938,9 @@ __device__ __forceinline__ void min_bytes16(uint32_t (&e)[4], uint32_t (&o)[4], 
 }
 
 template <int VEC>
-__global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdms, int64_t G,
-                                                 ActiveList act, uint8_t* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_combine(MapList maps, int64_t G, uint8_t* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int cnt = act.count;
+    const int cnt = maps.count;
     if constexpr (VEC == 16) {
         const int64_t nvec = G / 16;
         const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
@@ -953,8 +953,8 @@ __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdm
         for (int k = 0; k < 4; ++k) e0[k] = d0[k] = e1[k] = d1[k] = 0x00FF00FFu;
         int j = 0;
         for (; j + 2 <= cnt; j += 2) {
-            const uint8_t* pa = pdms + (int64_t)act.p[j] * G;
-            const uint8_t* pb = pdms + (int64_t)act.p[j + 1] * G;
+            const uint8_t* pa = maps.src[j];
+            const uint8_t* pb = maps.src[j + 1];
             const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
             const u32x4 b0 = load_nt16(pb + o0), b1 = load_nt16(pb + o1);
             min_bytes16(e0, d0, a0);
@@ -963,7 +963,7 @@ __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdm
             min_bytes16(e1, d1, b1);
         }
         if (j < cnt) {
-            const uint8_t* pa = pdms + (int64_t)act.p[j] * G;
+            const uint8_t* pa = maps.src[j];
             const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
             min_bytes16(e0, d0, a0);
             min_bytes16(e1, d1, a1);
@@ -986,7 +986,7 @@ __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdm
         if (off >= G) return;
         uint32_t e = 0x00FF00FFu, o = 0x00FF00FFu;
         for (int j = 0; j < cnt; ++j) {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(pdms + (int64_t)act.p[j] * G + off);
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(maps.src[j] + off);
             e = pk_min16(e, even_bytes(w));
             o = pk_min16(o, odd_bytes(w));
         }
@@ -994,8 +994,40 @@ __global__ void __launch_bounds__(256) k_combine(const uint8_t* __restrict__ pdm
     } else {
         if (t >= G) return;
         uint32_t m = 255u;
-        for (int j = 0; j < cnt; ++j) m = umin(m, (uint32_t)pdms[(int64_t)act.p[j] * G + t]);
+        for (int j = 0; j < cnt; ++j) m = umin(m, (uint32_t)maps.src[j][t]);
         out[t] = (uint8_t)m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_range_level: one level of the range table, dst[p] = min(src[p], src[p+h])
+// element-wise over maps of G bytes.  VEC = 16 needs G % 16 == 0 and 16-byte
+// aligned bases (a vector never straddles two maps); VEC = 1 otherwise.
+// ---------------------------------------------------------------------------
+template <int VEC>
+__global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__ src, int64_t h,
+                                                     uint8_t* __restrict__ dst, int64_t total,
+                                                     int64_t G) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (VEC == 16) {
+        const int64_t off = t * 16;
+        if (off >= total) return;
+        const u32x4 a = load_nt16(src + off);
+        const u32x4 b = load_nt16(src + off + h * G);
+        uint32_t e[4], o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = o[k] = 0x00FF00FFu;
+        min_bytes16(e, o, a);
+        min_bytes16(e, o, b);
+        uint4 r;
+        r.x = e[0] | (o[0] << 8);
+        r.y = e[1] | (o[1] << 8);
+        r.z = e[2] | (o[2] << 8);
+        r.w = e[3] | (o[3] << 8);
+        *reinterpret_cast<uint4*>(dst + off) = r;
+    } else {
+        if (t >= total) return;
+        dst[t] = (uint8_t)umin((uint32_t)src[t], (uint32_t)src[t + h * G]);
     }
 }
 
@@ -1430,14 +1462,28 @@ hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, 
     return hipSuccess;
 }
 
-hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
-                          int vec, hipStream_t s) {
+hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, int vec, hipStream_t s) {
     if (vec == 16)  // two 16-byte vectors per lane
-        k_combine<16><<<blocks_for((G / 16 + 1) / 2, 256), 256, 0, s>>>(pdms, G, act, out);
+        k_combine<16><<<blocks_for((G / 16 + 1) / 2, 256), 256, 0, s>>>(maps, G, out);
     else if (vec == 4)
-        k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(pdms, G, act, out);
+        k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(maps, G, out);
     else
-        k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(pdms, G, act, out);
+        k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(maps, G, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_level(const uint8_t* src, int64_t h, uint8_t* dst, int64_t count, int64_t G,
+                              int vec, hipStream_t s) {
+    const int64_t total = count * G;
+    if (vec == 16) {
+        const int64_t blocks = (total / 16 + 255) / 256;
+        if (blocks > INT32_MAX) return hipErrorInvalidValue;
+        k_range_level<16><<<(unsigned)blocks, 256, 0, s>>>(src, h, dst, total, G);
+    } else {
+        const int64_t blocks = (total + 255) / 256;
+        if (blocks > INT32_MAX) return hipErrorInvalidValue;
+        k_range_level<1><<<(unsigned)blocks, 256, 0, s>>>(src, h, dst, total, G);
+    }
     return hipGetLastError();
 }
 

@@ -18,9 +18,12 @@ struct Bounds {
 };
 
 // Indices of the active partitions (S), passed by value.
-struct ActiveList {
+// The maps one TF-update launch combines: pointers to G-byte maps (PDMs or
+// range-table maps), at most one per partition.
+struct MapList {
     int32_t count;
-    uint8_t p[256];
+    int32_t pad;
+    const uint8_t* src[256];
 };
 
 // Bit i set when alpha[i] != 0, passed by value.
@@ -123,7 +126,10 @@ hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vol
                               BatchSync* d_sync, const int64_t totals[3], int lines_mult,
                               int single, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
-hipError_t launch_combine(const uint8_t* pdms, int64_t G, const ActiveList& act, uint8_t* out,
-                          int vec, hipStream_t s);
+hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, int vec, hipStream_t s);
+// dst[p] = min(src[p], src[p + h]) for maps p = 0..count-1 (maps of G bytes,
+// contiguous): one level of the range table from the level below.
+hipError_t launch_range_level(const uint8_t* src, int64_t h, uint8_t* dst, int64_t count, int64_t G,
+                              int vec, hipStream_t s);
 
 }  // namespace pdm

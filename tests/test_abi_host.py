@@ -183,3 +183,90 @@ def test_batch_build_validation(lib):
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_rows, NULL) == L.PDM_E_INVAL
     bad_mode = ctypes.pointer(L.BatchConfig(0, 1, 0, 2))
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_mode, NULL) == L.PDM_E_INVAL
+
+
+def _level_first(n, k):
+    return sum(n - (1 << j) + 1 for j in range(1, k))
+
+
+def _expand(n, K, idx):
+    """Partitions covered by map index idx (PDM or range-table map)."""
+    if idx < n:
+        return {idx}
+    t = idx - n
+    for k in range(1, K + 1):
+        cnt = n - (1 << k) + 1
+        if t < cnt:
+            return set(range(t, t + (1 << k)))
+        t -= cnt
+    raise AssertionError(f"index {idx} beyond the table")
+
+
+def _runs(bits):
+    runs, a = [], None
+    for p, b in enumerate(bits + [False]):
+        if b and a is None:
+            a = p
+        if not b and a is not None:
+            runs.append((a, p - 1))
+            a = None
+    return runs
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 64, 200, 256])
+@pytest.mark.parametrize("max_level", [0, 1, 3, 8])
+def test_range_cover_is_exact(n, max_level):
+    """The maps chosen for an active set cover exactly S (no partition
+    outside S), take no more maps than |S|, and at most two per run while
+    runs fit the table; the table size is the sum of its levels."""
+    rng = np.random.default_rng(n * 31 + max_level)
+    K = 0
+    while K < max_level and (2 << K) <= n:
+        K += 1
+    assert L.range_table_maps(n, max_level) == _level_first(n, K + 1)
+    masks = []
+    for dens in (0.0, 0.05, 0.3, 0.7, 0.95, 1.0):
+        for _ in range(12):
+            masks.append(rng.random(n) < dens)
+    for a, b in ((0, n - 1), (n // 3, n // 2), (n - 1, n - 1)):  # single runs
+        bits = np.zeros(n, bool)
+        bits[a:b + 1] = True
+        masks.append(bits)
+    for bits in masks:
+        m = np.zeros(4, np.uint64)
+        for p in np.nonzero(bits)[0]:
+            m[p >> 6] |= np.uint64(1) << np.uint64(p & 63)
+        cov = L.range_cover(n, max_level, m)
+        got = set()
+        for idx in cov:
+            part = _expand(n, K, idx)
+            assert part <= set(np.nonzero(bits)[0].tolist()), (idx, part)
+            got |= part
+        assert got == set(np.nonzero(bits)[0].tolist())
+        assert len(cov) <= int(bits.sum())
+        runs = _runs(bits.tolist())
+        if all(b - a + 1 <= (2 << K) for a, b in runs):
+            assert len(cov) <= 2 * len(runs)
+
+
+def test_range_calls_validate(lib):
+    r = ctypes.byref
+    d = desc()
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    alpha = np.ones(256, np.float32)
+    pa = ctypes.c_void_p(alpha.ctypes.data)
+    assert L.lib().pdm_range_table_maps(0, 3) == -1 and L.lib().pdm_range_table_maps(257, 3) == -1
+    assert L.lib().pdm_range_table_maps(8, -1) == -1
+    assert lib.pdm_build_range_table(r(d), NULL, 8, 3, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_range_table(r(d), FAKE, 8, 3, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_build_range_table(r(d), FAKE, 8, 0, NULL, NULL) == L.PDM_OK  # K = 0: nothing to do
+    assert lib.pdm_tf_update_ranges(r(d), FAKE, NULL, pb, 8, 3, pa, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_tf_update_ranges(r(d), FAKE, FAKE, pb, 8, -1, pa, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    bad, pbad = _b([0, 100, 100, 256])
+    assert lib.pdm_tf_update_ranges(r(d), FAKE, FAKE, pbad, 3, 3, pa, FAKE, NULL, NULL) == L.PDM_E_INVAL
+    m = np.zeros(4, np.uint64)
+    out = np.zeros(256, np.int32)
+    cnt = ctypes.c_int32(0)
+    assert lib.pdm_range_cover(8, 3, None, ctypes.c_void_p(out.ctypes.data), r(cnt)) == L.PDM_E_INVAL
+    assert lib.pdm_range_cover(0, 3, ctypes.c_void_p(m.ctypes.data), ctypes.c_void_p(out.ctypes.data),
+                               r(cnt)) == L.PDM_E_INVAL

@@ -150,6 +150,50 @@ def test_partition_sweep_stag_beetle(pdm, orc, n, kind):
     run_all(pdm, orc, vol, 256, bounds, alphas, f"stag sweep {kind} n={n}")
 
 
+RANGE_CASES = [((64, 64, 64), np.uint8, 256, 8), ((23, 18, 30), np.uint16, 4096, 32),
+               ((40, 36, 64), np.uint8, 256, 256), ((17, 9, 13), np.uint8, 256, 19)]
+
+
+@pytest.mark.parametrize("max_level", [1, 3, 8])
+@pytest.mark.parametrize("shape,dtype,levels,n", RANGE_CASES,
+                         ids=["c1-like", "ragged-u16", "256-partitions", "odd-n"])
+def test_range_table_update(pdm, orc, shape, dtype, levels, n, max_level):
+    """Range-table maps against the oracle's definition, and the TF update
+    through the table against the oracle's D' (and the plain update): TFs
+    with ramps, scattered opacities (many runs of S), none and all."""
+    import torch
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + n + max_level)
+    bounds = W.uniform_bounds(levels, n)
+    say(f"[case] range table {shape} {np.dtype(dtype).name} n={n} max_level={max_level}")
+    v = pdm.Volume(pdm.to_device(vol), levels, bounds, voxel_dtype=dtype)
+    v.build()
+    v.build_range_table(max_level)
+    torch.cuda.synchronize()
+    want_pd = orc.pdms(vol, bounds, levels)
+    np.testing.assert_array_equal(pdm.from_device(v.pdms), want_pd)
+    table = orc.range_table(want_pd, max_level)
+    if len(table):
+        np.testing.assert_array_equal(pdm.from_device(v.table).reshape(table.shape), table)
+    else:
+        assert v.table is None
+    rng = np.random.default_rng(n)
+    alphas = tfs(levels, 5, n + 1)
+    for _ in range(6):
+        a = np.zeros(levels, np.float32)
+        a[rng.choice(levels, size=int(rng.integers(1, 40)), replace=False)] = 1.0
+        alphas.append(a)
+    plain = torch.empty_like(v.dist)
+    for k, alpha in enumerate(alphas):
+        m = v.update_tf_ranges(alpha)
+        m2 = v.update_tf(alpha, out=plain)
+        torch.cuda.synchronize()
+        dp, want_m = orc.tf_update(want_pd, bounds, alpha, levels)
+        np.testing.assert_array_equal(m, want_m)
+        np.testing.assert_array_equal(m2, want_m)
+        np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"D' via table, tf {k}")
+        assert torch.equal(v.dist.reshape(-1), plain.reshape(-1))
+
+
 def test_deterministic_and_no_out_of_bounds_writes(pdm, orc):
     """Outputs written into the middle of guarded buffers: guard bytes stay
     untouched and two runs give identical bytes."""

@@ -359,3 +359,35 @@ def test_thread_count_does_not_change_results(orc):
     finally:
         orc.set_threads(t0)
     np.testing.assert_array_equal(a, b)
+
+
+def _union_pdm(orc, vol, levels, lo, hi):
+    """PDM of the single partition [lo, hi] built from scratch: bounds that
+    tile [0, levels) with [lo, hi] as one partition."""
+    cuts = sorted({0, lo, hi + 1, levels})
+    k = cuts.index(lo)
+    return orc.pdms(vol, np.array(cuts, np.int32), levels)[k]
+
+
+@pytest.mark.parametrize("n,max_level", [(8, 3), (8, 1), (12, 8), (5, 2)])
+def test_range_table_maps_are_union_pdms(orc, n, max_level):
+    """Range-table map T_k[p] equals the PDM of the union of partitions
+    p .. p+2^k-1 computed from scratch (a fresh POM of the merged interval
+    and its distance transform), not only the min of the parts."""
+    rng = np.random.default_rng(n + max_level)
+    vol = np.zeros((20, 24, 28), np.uint8)
+    for _ in range(30):
+        z, y, x = rng.integers(0, 20), rng.integers(0, 24), rng.integers(0, 28)
+        vol[z, y, x] = rng.integers(1, 256)
+    bounds = W.uniform_bounds(256, n)
+    stack = orc.pdms(vol, bounds, 256)
+    table = orc.range_table(stack, max_level)
+    j = 0
+    k = 1
+    while k <= max_level and (1 << k) <= n:
+        for p in range(n - (1 << k) + 1):
+            want = _union_pdm(orc, vol, 256, int(bounds[p]), int(bounds[p + (1 << k)]) - 1)
+            np.testing.assert_array_equal(table[j], want, err_msg=f"k={k} p={p}")
+            j += 1
+        k += 1
+    assert j == len(table)
