@@ -4,6 +4,11 @@ benchmark times (one Volume, same calls, same stream).
 CT-like 512x512x460 u16 (12-bit), 32 partitions: bricks, all 32 PDMs, D' for
 all 200 TFs and D for 20 of them, each against the oracle element by element.
 
+Both: the range table (max_level 8) and D' through it for every TF (c2:
+the whole table against the oracle's definition; c3: 4 sampled table maps
+against PDMs of the merged partitions built from scratch, and D' through the
+table equal to the plain update's).
+
 Tube tree 1024x1024x795 u8, 64 partitions: bricks in full; PDMs of 6 sampled
 partitions (dense, sparse, empty); D' and D for 3 TFs, where the oracle's D'
 is the distance transform of the union of the active POMs (the union
@@ -51,13 +56,22 @@ def test_ct_like_512x512x460_u16(pdm, orc):
     say("[case] c2 oracle PDMs")
     want = orc.pdms(vol, bounds, L, brick_minmax=(bmin, bmax))
     np.testing.assert_array_equal(pdm.from_device(v.pdms), want)
+    say("[case] c2 range table")
+    v.build_range_table(8)
+    torch.cuda.synchronize()
+    table = orc.range_table(want, 8)
+    np.testing.assert_array_equal(pdm.from_device(v.table).reshape(table.shape), table)
     d = torch.empty_like(v.dist)
+    dr = torch.empty_like(v.dist)
     for k, alpha in enumerate(alphas):
         mask = v.update_tf(alpha)
+        mr = v.update_tf_ranges(alpha, out=dr)
         torch.cuda.synchronize()
         dp, m = orc.tf_update(want, bounds, alpha, L)
         np.testing.assert_array_equal(mask, m)
+        np.testing.assert_array_equal(mr, m)
         np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"D' tf {k}")
+        np.testing.assert_array_equal(pdm.from_device(dr), dp, err_msg=f"D' via table, tf {k}")
         if k % 10 == 0:
             say(f"[case] c2 full recompute tf {k}")
             v.full_recompute(alpha, out=d)
@@ -87,11 +101,28 @@ def test_tube_tree_1024x1024x795_u8(pdm, orc):
         lo, hi = int(bounds[p]), int(bounds[p + 1]) - 1
         want = orc.dt(orc.pom_range(bmin, bmax, lo, hi))
         np.testing.assert_array_equal(pdm.from_device(v.pdms[p]), want, err_msg=f"PDM {p}")
+    say("[case] c3 range table")
+    v.build_range_table(8)
+    torch.cuda.synchronize()
+    # sampled table maps against the PDM of the merged partition built from
+    # scratch (the union property), level k map p = partitions p .. p+2^k-1
+    first = {1: 0}
+    for k in range(2, 7):
+        first[k] = first[k - 1] + n - (1 << (k - 1)) + 1
+    for k, p in ((1, 0), (3, 5), (5, 20), (6, 0)):
+        lo, hi = int(bounds[p]), int(bounds[p + (1 << k)]) - 1
+        want = orc.dt(orc.pom_range(bmin, bmax, lo, hi))
+        np.testing.assert_array_equal(pdm.from_device(v.table[first[k] + p]), want,
+                                      err_msg=f"table level {k} map {p}")
     d = torch.empty_like(v.dist)
+    dr = torch.empty_like(v.dist)
     for k, alpha in enumerate(alphas):
         mask = v.update_tf(alpha)
+        mr = v.update_tf_ranges(alpha, out=dr)
         v.full_recompute(alpha, out=d)
         torch.cuda.synchronize()
+        assert torch.equal(dr, v.dist), f"D' via table differs, tf {k}"
+        np.testing.assert_array_equal(mr, mask)
         m = orc.active(bounds, alpha, L)
         np.testing.assert_array_equal(mask, m)
         dp_gpu, d_gpu = pdm.from_device(v.dist), pdm.from_device(d)

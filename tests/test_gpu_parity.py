@@ -194,6 +194,30 @@ def test_range_table_update(pdm, orc, shape, dtype, levels, n, max_level):
         assert torch.equal(v.dist.reshape(-1), plain.reshape(-1))
 
 
+def test_range_table_exact_mode(pdm, orc):
+    """The union property holds for the EXACT reading too (a voxel lies in
+    the union of intervals when it lies in one of them): the table over
+    EXACT PDMs gives the EXACT D'."""
+    import torch
+    vol = blocky((30, 26, 44), np.uint8, 256, seed=5)
+    bounds = W.uniform_bounds(256, 16)
+    say("[case] range table, EXACT reading")
+    v = pdm.Volume(pdm.to_device(vol), 256, bounds, mode=pdm.EXACT)
+    v.build()
+    v.build_range_table(8)
+    torch.cuda.synchronize()
+    want = orc.pdms(vol, bounds, 256, mode=orc.EXACT)
+    np.testing.assert_array_equal(pdm.from_device(v.pdms), want)
+    table = orc.range_table(want, 8)
+    np.testing.assert_array_equal(pdm.from_device(v.table).reshape(table.shape), table)
+    for k, alpha in enumerate(tfs(256, 6, 3)):
+        m = v.update_tf_ranges(alpha)
+        torch.cuda.synchronize()
+        dp, wm = orc.tf_update(want, bounds, alpha, 256)
+        np.testing.assert_array_equal(m, wm)
+        np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"tf {k}")
+
+
 def test_deterministic_and_no_out_of_bounds_writes(pdm, orc):
     """Outputs written into the middle of guarded buffers: guard bytes stay
     untouched and two runs give identical bytes."""
