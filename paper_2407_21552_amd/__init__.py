@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, PreparedVolume,
                    active_set, batch_build, batch_error, batch_tf_update, batch_tf_update_prepared,
                    batch_workspace_bytes, build_bricks, build_range_table, range_cover,
-                   range_table_maps, tf_update_ranges,
+                   range_table_maps, tf_update_ranges, tf_update_ranges_prepared,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
                    full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
@@ -28,7 +28,7 @@ from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, Prepare
 __all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build", "batch_error",
            "batch_tf_update", "batch_tf_update_prepared", "batch_workspace_bytes", "BATCH_MAX",
            "build_bricks", "build_partitions", "build_range_table", "range_cover",
-           "range_table_maps", "tf_update_ranges",
+           "range_table_maps", "tf_update_ranges", "tf_update_ranges_prepared",
            "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
            "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
            "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",
@@ -106,6 +106,7 @@ class Volume:
         self.table = (torch.empty((maps, self.bz, self.by, self.bx), dtype=torch.uint8,
                                   device=self.pdms.device) if maps > 0 else None)
         build_range_table(self.desc, self.pdms, self.n, self.range_level, self.table, stream)
+        self._prepared = None
 
     def update_tf_ranges(self, alpha, out=None, stream=None) -> np.ndarray:
         """update_tf through the range table (same D' and S mask)."""
@@ -114,9 +115,12 @@ class Volume:
 
     @property
     def prepared(self) -> PreparedVolume:
-        """This volume's fixed batched-update fields (built once)."""
+        """This volume's fixed update fields (built once; with the range table
+        when build_range_table has run)."""
         if getattr(self, "_prepared", None) is None:
-            self._prepared = PreparedVolume(self.desc, self.pdms, self.bounds)
+            self._prepared = PreparedVolume(self.desc, self.pdms, self.bounds,
+                                            getattr(self, "table", None),
+                                            getattr(self, "range_level", 0))
         return self._prepared
 
     def check_range(self) -> None:

@@ -407,9 +407,10 @@ class PreparedVolume:
     PDMs, partition borders), checked once so that a launch only adds the
     opacity tables and output maps.  The PDM tensor must stay alive and
     unchanged in place while the object is used."""
-    __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed")
+    __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed", "table", "max_level",
+                 "table_ptr")
 
-    def __init__(self, desc, pdms, bounds):
+    def __init__(self, desc, pdms, bounds, table=None, max_level: int = 0):
         self.desc = desc
         self.levels = int(desc.levels)
         self.G = grid_of(desc)[3]
@@ -420,6 +421,11 @@ class PreparedVolume:
         _dev_ptr(pdms, self.n * self.G, "pdms")
         self.pdms = pdms
         self.fixed = (ctypes.addressof(desc), pdms.data_ptr(), self.bounds.ctypes.data, self.n)
+        # optional range table (for tf_update_ranges_prepared)
+        self.max_level = int(max_level)
+        maps = range_table_maps(self.n, self.max_level)
+        self.table = table
+        self.table_ptr = _dev_ptr(table, maps * self.G, "table") if maps > 0 else ctypes.c_void_p(0)
 
 
 def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
@@ -448,6 +454,25 @@ def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
                                      _np_ptr(masks), _stream(stream)), "pdm_batch_tf_update")
     del keep
     return masks
+
+
+def tf_update_ranges_prepared(pv, alpha, dist, stream=None) -> np.ndarray:
+    """tf_update_ranges for a PreparedVolume that holds a range table;
+    returns the S mask."""
+    a = alpha
+    if not (type(a) is np.ndarray and a.dtype == np.float32 and a.flags.c_contiguous):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if a.shape != (pv.levels,):
+        raise ValueError(f"alpha must hold {pv.levels} float32 entries, got shape {a.shape}")
+    if not dist.is_cuda or not dist.is_contiguous() or dist.numel() * dist.element_size() != pv.G:
+        raise ValueError(f"dist: expected a contiguous device tensor of {pv.G} bytes")
+    m = np.zeros(4, np.uint64)
+    _, pd, b, n = pv.fixed
+    _check(lib().pdm_tf_update_ranges(ctypes.byref(pv.desc), ctypes.c_void_p(pd), pv.table_ptr,
+                                      ctypes.c_void_p(b), n, pv.max_level, _np_ptr(a),
+                                      ctypes.c_void_p(dist.data_ptr()), _np_ptr(m), _stream(stream)),
+           "pdm_tf_update_ranges")
+    return m
 
 
 # ------------------------------------------------------------- batched build

@@ -246,23 +246,32 @@ def requests_from(arrivals) -> List[Request]:
 
 class GpuExecutor(Executor):
     """Runs the server on the GPU through the C ABI.  Admission uploads the
-    voxels and builds bricks and PDMs on `admit_stream`; updates run on
-    `update_stream`, one batched launch per tick; each request gets its own
-    output map from a per-volume pool of `outputs_per_volume` buffers."""
+    voxels and builds bricks and PDMs (and, with `range_level`, the range
+    table) on `admit_stream`; updates run on `update_stream`, one batched
+    launch per tick (with `range_level`: one update through the table per
+    request); each request gets its own output map from a per-volume pool of
+    `outputs_per_volume` buffers."""
 
-    def __init__(self, outputs_per_volume: int = 8, keep_volume: bool = False):
+    def __init__(self, outputs_per_volume: int = 8, keep_volume: bool = False,
+                 range_level: Optional[int] = None):
         import torch
         self.torch = torch
         self.admit_stream = torch.cuda.Stream()
         self.update_stream = torch.cuda.Stream()
         self.outputs = int(outputs_per_volume)
         self.keep_volume = keep_volume
+        # with a range level, admission also builds each volume's range table
+        # and every request is one update through it (fewer maps read than
+        # the batched update of the active PDMs)
+        self.range_level = range_level
 
     def footprint(self, spec: VolumeSpec) -> int:
+        import paper_2407_21552_amd as pdm
         G = spec.bricks
         s = np.dtype(spec.dtype).itemsize
         vox = int(np.prod(spec.shape)) * s
-        return spec.n * G + self.outputs * G + 2 * G * s + (vox if self.keep_volume else 0)
+        table = pdm.range_table_maps(spec.n, self.range_level) * G if self.range_level else 0
+        return spec.n * G + table + self.outputs * G + 2 * G * s + (vox if self.keep_volume else 0)
 
     class Handle:
         pass
@@ -276,6 +285,8 @@ class GpuExecutor(Executor):
         with torch.cuda.stream(self.admit_stream):
             h.vol = pdm.Volume(pdm.to_device(vox), spec.levels, spec.bounds, voxel_dtype=spec.dtype)
             h.vol.build(self.admit_stream)
+            if self.range_level:
+                h.vol.build_range_table(self.range_level, self.admit_stream)
             h.outs = [torch.empty_like(h.vol.dist) for _ in range(self.outputs)]
             h.next_out = 0
             h.ready_ev = torch.cuda.Event()
@@ -283,6 +294,8 @@ class GpuExecutor(Executor):
         # PDMs and outputs are used on the update stream: keep the allocator
         # from reusing them while launches there may still run
         h.vol.pdms.record_stream(self.update_stream)
+        if self.range_level and h.vol.table is not None:
+            h.vol.table.record_stream(self.update_stream)
         for o in h.outs:
             o.record_stream(self.update_stream)
         # the server launches a volume's requests only once ready() has seen
@@ -311,7 +324,11 @@ class GpuExecutor(Executor):
             h.next_out = (h.next_out + 1) % len(h.outs)
             req.result = out
             entries.append((h.vol.prepared, alpha, out))
-        pdm.batch_tf_update_prepared(entries, self.update_stream)
+        if self.range_level:
+            for pv, alpha, out in entries:
+                pdm.tf_update_ranges_prepared(pv, alpha, out, self.update_stream)
+        else:
+            pdm.batch_tf_update_prepared(entries, self.update_stream)
         ev = torch.cuda.Event()
         ev.record(self.update_stream)
         return ev

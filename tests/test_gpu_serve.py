@@ -1,6 +1,7 @@
 """The server on the GPU: every result of a served Poisson stream (batched
 with other volumes' requests, overlapping admissions and evictions) equals
-the same update run alone, byte for byte."""
+the same update run alone, byte for byte; with the batched update of the
+active PDMs and with updates through range tables."""
 import collections
 
 import numpy as np
@@ -11,7 +12,8 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone(orc):
+@pytest.mark.parametrize("range_level", [None, 6], ids=["batched", "range-tables"])
+def test_served_results_equal_alone(orc, range_level):
     import torch
     import paper_2407_21552_amd as pdm
     from paper_2407_21552_amd.serve import GpuExecutor, Server, VolumeSpec, requests_from
@@ -29,9 +31,10 @@ def test_served_results_equal_alone(orc):
     sched = requests_from(W.poisson_requests(5000.0, 0.06, list(cat), {k: cat[k].levels for k in cat},
                                              seed=11))
     per_vol = collections.Counter(r.vol_id for r in sched)
-    ex = GpuExecutor(outputs_per_volume=max(per_vol.values()) + 1)
+    ex = GpuExecutor(outputs_per_volume=max(per_vol.values()) + 1, range_level=range_level)
     srv = Server(ex, cat, budget_bytes=10**10, max_slots=4)   # 6 volumes, 4 slots: evictions
-    print(f"[case] serving {len(sched)} requests over {len(cat)} volumes", flush=True)
+    print(f"[case] serving {len(sched)} requests over {len(cat)} volumes, range_level {range_level}",
+          flush=True)
     srv.run(sched, timeout=60)
     torch.cuda.synchronize()
     rep = srv.report()
