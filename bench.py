@@ -381,8 +381,9 @@ def main():
 
 
 def run_batched(args):
-    """48 uneven volumes: persistent batched build and one-launch TF update
-    against per-volume launch loops."""
+    """48 uneven volumes: the batched build (launch shape and grouped or
+    single launch from the autotuner) and the one-launch TF update against
+    per-volume launch loops."""
     import torch
     import paper_2407_21552_amd as pdm
     from paper_2407_21552_amd import autotune

@@ -16,9 +16,16 @@
 //                   to the nearest occupied brick along x (wave ballots).
 //   k_plain_x       volume + TF -> occupancy and x distance (plain method).
 //   k_dist_axis     x distances -> full chessboard distances: 1-D max-min pass
-//                   along y or z, one lane per line, linear-time scan.
-//   k_combine       masked min over the active PDM streams, 16 bytes per lane.
+//                   along y or z, one lane per line, linear-time scan, lines
+//                   staged in LDS (few lines: one map).
+//   k_dist_global   the same pass on global memory (many lines: all maps).
+//   k_combine       min over a list of G-byte maps (the active PDMs, or the
+//                   range-table maps covering them), 16 bytes per lane.
+//   k_range_level   one level of the range table: min of two maps.
 //   k_batch_combine the TF updates of up to 48 volumes in one launch.
+//   k_batch_rows, k_batch_scan, k_batch_single
+//                   batched build of up to 48 volumes: grouped launches per
+//                   phase, or one cooperative launch with grid barriers.
 //   k_pom_exact_x   EXACT reading: per-brick partition masks from the voxels,
 //                   then the x distances of every partition.
 //   k_plain_exact_x EXACT reading of the plain method's occupancy.
