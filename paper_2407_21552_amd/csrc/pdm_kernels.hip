@@ -821,6 +821,40 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
         if (active) p[(int64_t)c * step] = (uint8_t)out;
     }
 }
+
+// The one-sided pass over steps [ib, ie) of a line held in an LDS column
+// col[k * cs], with the scan state carried in and out (the split pass below
+// runs it in phases).  Values are clamped at vmax before their step; with
+// `track` the raw values read are folded into raw_min.
+template <int CH>
+__device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib, int ie, int vmax,
+                                                    bool track, uint8_t* __restrict__ tbl, int& v,
+                                                    int& W, int& t, int& ra, int& rb, int& ip,
+                                                    bool& take, bool& adv, bool& eq, int& raw_min) {
+    using P = uint8_t;  // table entry type of PDM_SCAN_STEP
+    const int lane = threadIdx.x;
+    int c = ib;
+    for (; c + CH <= ie; c += CH) {
+        int f[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = col[(c + k) * cs];
+            if (track) raw_min = min(raw_min, r);
+            f[k] = min(r, vmax);
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) col[(c + k) * cs] = (uint8_t)f[k];
+    }
+    for (; c < ie; ++c) {
+        const int r = col[c * cs];
+        if (track) raw_min = min(raw_min, r);
+        int out;
+        PDM_SCAN_STEP(c, min(r, vmax), out);
+        col[c * cs] = (uint8_t)out;
+    }
+}
 #undef PDM_SCAN_STEP
 
 // Work-groups are handed to the 8 XCDs round-robin (work-group b runs on XCD
@@ -890,6 +924,91 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_axis(uint8_t* __restrict__ 
     } else if (active) {
         uint8_t* line = maps + line_offset(l, Bx, inner, plane, G);
         for (int r = 0; r < m; ++r) line[(int64_t)r * stride] = tile[r * kScanLanes + lane];
+    }
+}
+
+// Split pass, 32 lines per wave: lanes 0-31 run the forward one-sided pass
+// of lines 0-31 and lanes 32-63 the backward pass of the same lines at the
+// same time, each first over its half of the line (phase 1), then over the
+// half the other lane has finished (phase 2).  A one-sided pass over the
+// other direction's results gives the two-sided result, so [h, m) ends
+// with the values the forward lane wrote in phase 2 and [0, h) with the
+// backward lane's: both two-sided.  Halves never touch the same position in
+// the same step; for odd m the backward lane's last phase-1 step and the
+// forward lane's first phase-2 step (both at position h) run one after the
+// other.  Values are clamped at vmax = min(m, 255) (table rows vmax + 3): a
+// pass over min(f, m) gives min(g, m), and a result of m means every value
+// of the line is >= m, where the two-sided result is the line's minimum.
+// The chain is half that of k_dist_axis for 1.5x its LDS per line; the
+// launcher takes it when every work-group fits at once.
+__global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__ maps, int64_t lines,
+                                                           int Bx, int inner, int64_t plane,
+                                                           int64_t stride, int m, int64_t G,
+                                                           int rows, int wide) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t* tbl = smem;
+    uint8_t* tile = smem + ((rows * kPitch + 15) & ~15);  // [pos][32]
+    const int lane = threadIdx.x;
+    const int half = lane >> 5, li = lane & 31;
+    const int64_t l0 = xcd_item(blockIdx.x) * 32;
+    if (l0 >= lines) return;
+    const int64_t l = l0 + li;
+    const bool active = l < lines;
+    if (wide) {
+        // 32 lines = x0..x0+31 of one row: two 16-byte pieces per position
+        const uint8_t* base = maps + line_offset(l0, Bx, inner, plane, G);
+        const int q = lane & 1;
+        for (int r = lane >> 1; r < m; r += 32)
+            *reinterpret_cast<uint4*>(&tile[r * 32 + 16 * q]) =
+                *reinterpret_cast<const uint4*>(base + (int64_t)r * stride + 16 * q);
+    } else {
+        const uint8_t* line = maps + (active ? line_offset(l, Bx, inner, plane, G) : 0);
+        for (int r = half; r < m; r += 2) tile[r * 32 + li] = active ? line[(int64_t)r * stride] : (uint8_t)0;
+    }
+    {
+        const int bytes = ((rows * kPitch + 15) & ~15) / 16;
+        uint4* t4 = reinterpret_cast<uint4*>(tbl);
+        for (int i = lane; i < bytes; i += kScanLanes) t4[i] = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    const int vmax = min(m, 255);
+    const int h = m / 2;
+    uint8_t* col = half == 0 ? &tile[li] : &tile[(m - 1) * 32 + li];
+    const int cs = half == 0 ? 32 : -32;
+    int raw_min = col[0];
+    int v = min(raw_min, vmax);
+    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
+    bool take = false, adv = false, eq = false;
+    // phase 1: forward lanes steps [1, h), backward lanes [1, m - h)
+    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, t, ra, rb, ip, take, adv, eq,
+                            raw_min);
+    if (m - h > h && half == 1)
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, t, ra, rb, ip, take, adv,
+                               eq, raw_min);
+    __builtin_amdgcn_wave_barrier();
+    const int lmin = min(raw_min, __shfl_xor(raw_min, 32, kScanLanes));
+    // phase 2: forward lanes steps [h, m), backward lanes [m - h, m)
+    if (m - h > h && half == 0)
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, t, ra, rb, ip, take, adv,
+                               eq, raw_min);
+    __builtin_amdgcn_wave_barrier();
+    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, t, ra, rb, ip, take, adv, eq,
+                            raw_min);
+    // every value of the line >= vmax: the two-sided result is the minimum
+    if (lmin >= vmax) {
+        const int n = half == 0 ? m - h : h;  // this lane's phase-2 positions
+        for (int k = 0; k < n; ++k) col[(m - 1 - k) * cs] = (uint8_t)lmin;
+    }
+    __syncthreads();
+    if (wide) {
+        uint8_t* base = maps + line_offset(l0, Bx, inner, plane, G);
+        const int q = lane & 1;
+        for (int r = lane >> 1; r < m; r += 32)
+            *reinterpret_cast<uint4*>(base + (int64_t)r * stride + 16 * q) =
+                *reinterpret_cast<const uint4*>(&tile[r * 32 + 16 * q]);
+    } else if (active) {
+        uint8_t* line = maps + line_offset(l, Bx, inner, plane, G);
+        for (int r = half; r < m; r += 2) line[(int64_t)r * stride] = tile[r * 32 + li];
     }
 }
 
@@ -1450,11 +1569,29 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
         k_dist_global<uint8_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
             maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
     } else {
-        // 16-byte staging: groups of 64 lines never straddle a row, rows and
-        // the map base are 16-byte aligned
-        const int wide = Bx % kScanLanes == 0 && a.stride % 16 == 0 && ((uintptr_t)maps & 15) == 0;
-        k_dist_axis<<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, a.plane,
-                                                            a.stride, a.m, G, wide);
+        // the split pass when every one of its work-groups is resident at once
+        // (one round of half-length chains); otherwise 64 lines per wave
+        const int rows = min(a.m, 255) + 3;
+        const size_t lds = (size_t)((rows * kPitch + 15) & ~15) + (size_t)32 * a.m;
+        const int64_t split_tiles = (a.lines + 31) / 32;
+        const int64_t split_blocks = (split_tiles + kXcdSpan - 1) / kXcdSpan * kXcdSpan;
+        int dev = 0, cus = 0, per_cu = 0;
+        bool split = hipGetDevice(&dev) == hipSuccess &&
+                     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                     hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dist_split, kScanLanes,
+                                                                  lds) == hipSuccess &&
+                     (int64_t)per_cu * cus >= split_tiles && split_blocks <= INT32_MAX;
+        if (split) {
+            const int wide = Bx % 32 == 0 && a.stride % 16 == 0 && ((uintptr_t)maps & 15) == 0;
+            k_dist_split<<<(unsigned)split_blocks, kScanLanes, lds, s>>>(
+                maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G, rows, wide);
+        } else {
+            // 16-byte staging: groups of 64 lines never straddle a row, rows
+            // and the map base are 16-byte aligned
+            const int wide = Bx % kScanLanes == 0 && a.stride % 16 == 0 && ((uintptr_t)maps & 15) == 0;
+            k_dist_axis<<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, a.plane,
+                                                                a.stride, a.m, G, wide);
+        }
     }
     return hipGetLastError();
 }
