@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import struct
 
 import numpy as np
 
@@ -394,12 +395,15 @@ def batch_tf_update(items, stream=None) -> np.ndarray:
     return masks
 
 
-_BATCH_UPDATE_DTYPE = np.dtype({
-    "names": ["v", "d_pdms", "h_bounds", "n", "h_alpha", "d_dist"],
-    "formats": [np.uint64, np.uint64, np.uint64, np.int32, np.uint64, np.uint64],
-    "offsets": [BatchUpdate.v.offset, BatchUpdate.d_pdms.offset, BatchUpdate.h_bounds.offset,
-                BatchUpdate.n.offset, BatchUpdate.h_alpha.offset, BatchUpdate.d_dist.offset],
-    "itemsize": ctypes.sizeof(BatchUpdate)})
+# Rows of pdm_batch_update packed without ctypes objects: the fixed part of a
+# prepared volume (descriptor, PDMs, borders, n) once, the two per-call
+# pointers (opacity table, output map) per launch.
+_BATCH_FIXED = struct.Struct("<QQQi4x")
+_BATCH_PTRS = struct.Struct("<QQ")
+assert (BatchUpdate.v.offset, BatchUpdate.d_pdms.offset, BatchUpdate.h_bounds.offset,
+        BatchUpdate.n.offset, BatchUpdate.h_alpha.offset, BatchUpdate.d_dist.offset,
+        ctypes.sizeof(BatchUpdate)) == (0, 8, 16, 24, 32, 40, _BATCH_FIXED.size + _BATCH_PTRS.size)
+_F32 = np.dtype(np.float32)
 
 
 class PreparedVolume:
@@ -407,8 +411,8 @@ class PreparedVolume:
     PDMs, partition borders), checked once so that a launch only adds the
     opacity tables and output maps.  The PDM tensor must stay alive and
     unchanged in place while the object is used."""
-    __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed", "table", "max_level",
-                 "table_ptr")
+    __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed", "packed", "table",
+                 "max_level", "table_ptr")
 
     def __init__(self, desc, pdms, bounds, table=None, max_level: int = 0):
         self.desc = desc
@@ -421,11 +425,25 @@ class PreparedVolume:
         _dev_ptr(pdms, self.n * self.G, "pdms")
         self.pdms = pdms
         self.fixed = (ctypes.addressof(desc), pdms.data_ptr(), self.bounds.ctypes.data, self.n)
+        self.packed = _BATCH_FIXED.pack(*self.fixed)
         # optional range table (for tf_update_ranges_prepared)
         self.max_level = int(max_level)
         maps = range_table_maps(self.n, self.max_level)
         self.table = table
         self.table_ptr = _dev_ptr(table, maps * self.G, "table") if maps > 0 else ctypes.c_void_p(0)
+
+
+def _opacity_table(alpha, levels: int, what: str):
+    """(array, host address) of `alpha` as C-contiguous float32 of `levels`
+    entries; an array that already is one is used in place."""
+    a = alpha
+    if type(a) is not np.ndarray or a.dtype is not _F32 or not a.flags.c_contiguous:
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if a.shape != (levels,):
+        raise ValueError(f"{what} must hold {levels} float32 entries, got shape {a.shape}")
+    if a.flags.writeable:  # the buffer protocol is the cheap route to the address
+        return a, ctypes.addressof(ctypes.c_char.from_buffer(a))
+    return a, a.ctypes.data
 
 
 def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
@@ -436,22 +454,17 @@ def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
     count = len(entries)
     if not 1 <= count <= BATCH_MAX:
         raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
-    arr = np.empty(count, _BATCH_UPDATE_DTYPE)
-    keep = []
+    rows, keep = [], []
     for k, (pv, alpha, dist) in enumerate(entries):
-        a = alpha
-        if not (type(a) is np.ndarray and a.dtype == np.float32 and a.flags.c_contiguous):
-            a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
-        if a.shape != (pv.levels,):
-            raise ValueError(f"alpha {k} must hold {pv.levels} float32 entries, got shape {a.shape}")
-        if not dist.is_cuda or not dist.is_contiguous() or dist.numel() * dist.element_size() != pv.G:
-            raise ValueError(f"dist {k}: expected a contiguous device tensor of {pv.G} bytes")
+        a, ap = _opacity_table(alpha, pv.levels, f"alpha {k}")
         keep.append(a)
-        v, pd, b, n = pv.fixed
-        arr[k] = (v, pd, b, n, a.ctypes.data, dist.data_ptr())
+        if dist.nbytes != pv.G or not dist.is_cuda or not dist.is_contiguous():
+            raise ValueError(f"dist {k}: expected a contiguous device tensor of {pv.G} bytes")
+        rows.append(pv.packed + _BATCH_PTRS.pack(ap, dist.data_ptr()))
+    arr = (BatchUpdate * count).from_buffer_copy(b"".join(rows))
     masks = np.zeros((count, 4), np.uint64)
-    _check(lib().pdm_batch_tf_update(arr.ctypes.data_as(ctypes.POINTER(BatchUpdate)), count,
-                                     _np_ptr(masks), _stream(stream)), "pdm_batch_tf_update")
+    _check(lib().pdm_batch_tf_update(arr, count, _np_ptr(masks), _stream(stream)),
+           "pdm_batch_tf_update")
     del keep
     return masks
 
@@ -459,17 +472,13 @@ def batch_tf_update_prepared(entries, stream=None) -> np.ndarray:
 def tf_update_ranges_prepared(pv, alpha, dist, stream=None) -> np.ndarray:
     """tf_update_ranges for a PreparedVolume that holds a range table;
     returns the S mask."""
-    a = alpha
-    if not (type(a) is np.ndarray and a.dtype == np.float32 and a.flags.c_contiguous):
-        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
-    if a.shape != (pv.levels,):
-        raise ValueError(f"alpha must hold {pv.levels} float32 entries, got shape {a.shape}")
-    if not dist.is_cuda or not dist.is_contiguous() or dist.numel() * dist.element_size() != pv.G:
+    a, ap = _opacity_table(alpha, pv.levels, "alpha")
+    if dist.nbytes != pv.G or not dist.is_cuda or not dist.is_contiguous():
         raise ValueError(f"dist: expected a contiguous device tensor of {pv.G} bytes")
     m = np.zeros(4, np.uint64)
     _, pd, b, n = pv.fixed
     _check(lib().pdm_tf_update_ranges(ctypes.byref(pv.desc), ctypes.c_void_p(pd), pv.table_ptr,
-                                      ctypes.c_void_p(b), n, pv.max_level, _np_ptr(a),
+                                      ctypes.c_void_p(b), n, pv.max_level, ctypes.c_void_p(ap),
                                       ctypes.c_void_p(dist.data_ptr()), _np_ptr(m), _stream(stream)),
            "pdm_tf_update_ranges")
     return m

@@ -1040,18 +1040,19 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
 // ---------------------------------------------------------------------------
 // k_combine: D'[c] = min over the listed maps of map[c] (the active
 // partitions' PDMs, or range-table maps covering them).
-// VEC = 16: each lane owns two 16-byte vectors, `nthr` vectors apart so that
-// every load instruction of a wave covers 1 KiB of one stream; partitions are
-// taken two at a time, so four 16-byte non-temporal loads are in flight per
-// lane (the PDMs are streamed once per update and do not fit in the caches).
-// The running minimum is kept as even/odd byte pairs in packed u16 lanes.
-// VEC = 4 and VEC = 1 serve sizes or pointers that are not 16-byte aligned.
-// An empty list writes 255.
+// A map of G >= 16 bytes is cut into ceil(G/16) chunks of 16 bytes; chunk c
+// starts at min(16c, G - 16), so the last chunk ends at G and overlaps its
+// neighbour, whose lane writes the same bytes there.  Chunks are loaded and
+// stored at any byte alignment (the hardware serves unaligned vector
+// accesses), so every size and every base pointer take this path; maps of
+// fewer than 16 bytes take a byte path (VEC = 1).
+// Each lane owns two chunks, `nthr` chunks apart so that every load
+// instruction of a wave covers 1 KiB of one stream; maps are taken two at a
+// time, so four 16-byte non-temporal loads are in flight per lane (the maps
+// are streamed once per update and do not fit in the caches).  The running
+// minimum is kept as even/odd byte pairs in packed u16 lanes.  An empty list
+// writes 255.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ u32x4 load_nt16(const uint8_t* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-}
-
 __device__ __forceinline__ void min_bytes16(uint32_t (&e)[4], uint32_t (&o)[4], const u32x4 w) {
     e[0] = pk_min16(e[0], even_bytes(w.x));
     o[0] = pk_min16(o[0], odd_bytes(w.x));
@@ -1063,60 +1064,79 @@ __device__ __forceinline__ void min_bytes16(uint32_t (&e)[4], uint32_t (&o)[4], 
     o[3] = pk_min16(o[3], odd_bytes(w.w));
 }
 
-template <int VEC>
-__global__ void __launch_bounds__(256) k_combine(MapList maps, int64_t G, uint8_t* __restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int cnt = maps.count;
-    if constexpr (VEC == 16) {
-        const int64_t nvec = G / 16;
-        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-        const int64_t i0 = t, i1 = t + nthr;
-        if (i0 >= nvec) return;
-        const bool two = i1 < nvec;
-        const int64_t o0 = i0 * 16, o1 = two ? i1 * 16 : o0;
-        uint32_t e0[4], d0[4], e1[4], d1[4];
+__device__ __forceinline__ int64_t chunk_off(int64_t c, int64_t G) {
+    return 16 * c < G - 16 ? 16 * c : G - 16;
+}
+
+__device__ __forceinline__ void store16_u(PDM_GLB uint8_t* p, const u32x4 v) {
+    *reinterpret_cast<PDM_GLB u32x4_u*>(p) = v;
+}
+
+// Minimum of the chunks at o0 and o1 over the maps added so far.
+struct ChunkMin2 {
+    uint32_t e0[4], d0[4], e1[4], d1[4];
+
+    __device__ __forceinline__ ChunkMin2() {
 #pragma unroll
         for (int k = 0; k < 4; ++k) e0[k] = d0[k] = e1[k] = d1[k] = 0x00FF00FFu;
-        int j = 0;
-        for (; j + 2 <= cnt; j += 2) {
-            const uint8_t* pa = maps.src[j];
-            const uint8_t* pb = maps.src[j + 1];
-            const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
-            const u32x4 b0 = load_nt16(pb + o0), b1 = load_nt16(pb + o1);
-            min_bytes16(e0, d0, a0);
-            min_bytes16(e1, d1, a1);
-            min_bytes16(e0, d0, b0);
-            min_bytes16(e1, d1, b1);
-        }
-        if (j < cnt) {
-            const uint8_t* pa = maps.src[j];
-            const u32x4 a0 = load_nt16(pa + o0), a1 = load_nt16(pa + o1);
-            min_bytes16(e0, d0, a0);
-            min_bytes16(e1, d1, a1);
-        }
-        uint4 r;
+    }
+    __device__ __forceinline__ void add(const PDM_GLB uint8_t* a, int64_t o0, int64_t o1) {
+        const u32x4 a0 = load16_nt(a + o0), a1 = load16_nt(a + o1);
+        min_bytes16(e0, d0, a0);
+        min_bytes16(e1, d1, a1);
+    }
+    // two maps: all four loads issued before the first minimum
+    __device__ __forceinline__ void add2(const PDM_GLB uint8_t* a, const PDM_GLB uint8_t* b,
+                                         int64_t o0, int64_t o1) {
+        const u32x4 a0 = load16_nt(a + o0), a1 = load16_nt(a + o1);
+        const u32x4 b0 = load16_nt(b + o0), b1 = load16_nt(b + o1);
+        min_bytes16(e0, d0, a0);
+        min_bytes16(e1, d1, a1);
+        min_bytes16(e0, d0, b0);
+        min_bytes16(e1, d1, b1);
+    }
+    __device__ __forceinline__ void store(PDM_GLB uint8_t* out, int64_t o0, int64_t o1, bool two) const {
+        u32x4 r;
         r.x = e0[0] | (d0[0] << 8);
         r.y = e0[1] | (d0[1] << 8);
         r.z = e0[2] | (d0[2] << 8);
         r.w = e0[3] | (d0[3] << 8);
-        *reinterpret_cast<uint4*>(out + o0) = r;
+        store16_u(out + o0, r);
         if (two) {
             r.x = e1[0] | (d1[0] << 8);
             r.y = e1[1] | (d1[1] << 8);
             r.z = e1[2] | (d1[2] << 8);
             r.w = e1[3] | (d1[3] << 8);
-            *reinterpret_cast<uint4*>(out + o1) = r;
+            store16_u(out + o1, r);
         }
-    } else if constexpr (VEC == 4) {
-        const int64_t off = t * 4;
-        if (off >= G) return;
-        uint32_t e = 0x00FF00FFu, o = 0x00FF00FFu;
-        for (int j = 0; j < cnt; ++j) {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(maps.src[j] + off);
-            e = pk_min16(e, even_bytes(w));
-            o = pk_min16(o, odd_bytes(w));
-        }
-        *reinterpret_cast<uint32_t*>(out + off) = e | (o << 8);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ const PDM_GLB T* glb(const T* p) {
+    return (const PDM_GLB T*)p;
+}
+template <typename T>
+__device__ __forceinline__ PDM_GLB T* glb(T* p) {
+    return (PDM_GLB T*)p;
+}
+
+template <int VEC>
+__global__ void __launch_bounds__(256) k_combine(MapList maps, int64_t G, uint8_t* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = maps.count;
+    if constexpr (VEC == 16) {
+        const int64_t nch = (G + 15) / 16;
+        const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+        const int64_t i0 = t, i1 = t + nthr;
+        if (i0 >= nch) return;
+        const bool two = i1 < nch;
+        const int64_t o0 = chunk_off(i0, G), o1 = two ? chunk_off(i1, G) : o0;
+        ChunkMin2 acc;
+        int j = 0;
+        for (; j + 2 <= cnt; j += 2) acc.add2(glb(maps.src[j]), glb(maps.src[j + 1]), o0, o1);
+        if (j < cnt) acc.add(glb(maps.src[j]), o0, o1);
+        acc.store(glb(out), o0, o1, two);
     } else {
         if (t >= G) return;
         uint32_t m = 255u;
@@ -1127,8 +1147,9 @@ __global__ void __launch_bounds__(256) k_combine(MapList maps, int64_t G, uint8_
 
 // ---------------------------------------------------------------------------
 // k_range_level: one level of the range table, dst[p] = min(src[p], src[p+h])
-// element-wise over maps of G bytes.  VEC = 16 needs G % 16 == 0 and 16-byte
-// aligned bases (a vector never straddles two maps); VEC = 1 otherwise.
+// element-wise over maps of G bytes, i.e. over the flat `total` bytes of the
+// destination maps.  VEC = 16 cuts the flat range into 16-byte chunks as
+// k_combine does (total >= 16, any alignment); VEC = 1 otherwise.
 // ---------------------------------------------------------------------------
 template <int VEC>
 __global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__ src, int64_t h,
@@ -1136,21 +1157,12 @@ __global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__
                                                      int64_t G) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if constexpr (VEC == 16) {
-        const int64_t off = t * 16;
-        if (off >= total) return;
-        const u32x4 a = load_nt16(src + off);
-        const u32x4 b = load_nt16(src + off + h * G);
-        uint32_t e[4], o[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = o[k] = 0x00FF00FFu;
-        min_bytes16(e, o, a);
-        min_bytes16(e, o, b);
-        uint4 r;
-        r.x = e[0] | (o[0] << 8);
-        r.y = e[1] | (o[1] << 8);
-        r.z = e[2] | (o[2] << 8);
-        r.w = e[3] | (o[3] << 8);
-        *reinterpret_cast<uint4*>(dst + off) = r;
+        if (t >= (total + 15) / 16) return;
+        const int64_t off = chunk_off(t, total);
+        const PDM_GLB uint8_t* s = glb(src);
+        ChunkMin2 acc;
+        acc.add2(s + off, s + off + h * G, 0, 0);
+        acc.store(glb(dst), off, off, false);
     } else {
         if (t >= total) return;
         dst[t] = (uint8_t)umin((uint32_t)src[t], (uint32_t)src[t + h * G]);
@@ -1160,54 +1172,70 @@ __global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__
 // ---------------------------------------------------------------------------
 // k_batch_combine: the TF update of many volumes in one launch.  Each volume
 // has its own PDM stack, output map and active set (a 256-bit mask); blocks
-// are assigned to volumes by the prefix counts in first_block, so every
-// work-group serves one volume.  A lane owns 16 consecutive bricks; volumes
-// whose size or pointers are not 16-byte aligned take a byte-wise path.
+// are assigned to volumes by the prefix counts in first_block (a binary
+// search), so every work-group serves one volume and its control values are
+// uniform.  Within a volume the work is that of k_combine: two 16-byte chunks
+// per lane at any size and alignment, the active PDMs taken two at a time;
+// volumes of fewer than 16 bricks take a byte path.
 // ---------------------------------------------------------------------------
+// The set bits of a 256-bit mask in increasing order: the current word and
+// its index are kept (in scalar registers: the mask is uniform), the next
+// word is read from the argument when one runs out.
+struct BitWalk {
+    const uint64_t* words;
+    uint64_t cur;
+    int w;
+
+    __device__ __forceinline__ explicit BitWalk(const uint64_t* m) : words(m), cur(m[0]), w(0) {}
+    // next set bit, or -1 when none is left
+    __device__ __forceinline__ int next() {
+        while (cur == 0) {
+            if (++w == 4) return -1;
+            cur = words[w];
+        }
+        const int p = 64 * w + (__ffsll((unsigned long long)cur) - 1);
+        cur &= cur - 1;
+        return p;
+    }
+};
+
 __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
-    int k = 0;
-    while (k + 1 < a.count && (int64_t)blockIdx.x >= a.it[k + 1].first_block) ++k;
-    const uint8_t* __restrict__ pdms = a.it[k].pdms;
-    uint8_t* __restrict__ out = a.it[k].out;
-    const int64_t G = a.it[k].G;
-    const int64_t off = (((int64_t)blockIdx.x - a.it[k].first_block) * blockDim.x + threadIdx.x) * 16;
-    if (off >= G) return;
-    if (a.it[k].vec16) {
-        uint32_t e[4], o[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) e[j] = o[j] = 0x00FF00FFu;
-        for (int w = 0; w < 4; ++w) {
-            uint64_t m = a.it[k].mask[w];
-            while (m) {
-                const int p = 64 * w + (__ffsll((unsigned long long)m) - 1);
-                m &= m - 1;
-                min_bytes16(e, o, load_nt16(pdms + (int64_t)p * G + off));
+    int lo = 0, hi = a.count - 1;  // last volume with first_block <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)blockIdx.x >= a.it[mid].first_block) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchItem& it = a.it[lo];
+    const PDM_GLB uint8_t* pdms = glb(it.pdms);
+    PDM_GLB uint8_t* out = glb(it.out);
+    const int64_t G = it.G;
+    const int64_t t = ((int64_t)blockIdx.x - it.first_block) * blockDim.x + threadIdx.x;
+    BitWalk bits(it.mask);
+    if (G >= 16) {
+        const int64_t nch = (G + 15) / 16;
+        const int64_t nthr = it.blocks * (int64_t)blockDim.x;
+        const int64_t i0 = t, i1 = t + nthr;
+        if (i0 >= nch) return;
+        const bool two = i1 < nch;
+        const int64_t o0 = chunk_off(i0, G), o1 = two ? chunk_off(i1, G) : o0;
+        ChunkMin2 acc;
+        for (;;) {
+            const int pa = bits.next();
+            if (pa < 0) break;
+            const int pb = bits.next();
+            if (pb < 0) {
+                acc.add(pdms + (int64_t)pa * G, o0, o1);
+                break;
             }
+            acc.add2(pdms + (int64_t)pa * G, pdms + (int64_t)pb * G, o0, o1);
         }
-        uint4 r;
-        r.x = e[0] | (o[0] << 8);
-        r.y = e[1] | (o[1] << 8);
-        r.z = e[2] | (o[2] << 8);
-        r.w = e[3] | (o[3] << 8);
-        *reinterpret_cast<uint4*>(out + off) = r;
+        acc.store(out, o0, o1, two);
     } else {
-        const int nb = (int)min((int64_t)16, G - off);
-        uint32_t mm[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) mm[j] = 255u;
-        for (int w = 0; w < 4; ++w) {
-            uint64_t m = a.it[k].mask[w];
-            while (m) {
-                const int p = 64 * w + (__ffsll((unsigned long long)m) - 1);
-                m &= m - 1;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (j < nb) mm[j] = umin(mm[j], (uint32_t)pdms[(int64_t)p * G + off + j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (j < nb) out[off + j] = (uint8_t)mm[j];
+        if (t >= G) return;
+        uint32_t v = 255u;
+        for (int p = bits.next(); p >= 0; p = bits.next()) v = umin(v, (uint32_t)pdms[(int64_t)p * G + t]);
+        out[t] = (uint8_t)v;
     }
 }
 
@@ -1606,21 +1634,19 @@ hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, 
     return hipSuccess;
 }
 
-hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, int vec, hipStream_t s) {
-    if (vec == 16)  // two 16-byte vectors per lane
-        k_combine<16><<<blocks_for((G / 16 + 1) / 2, 256), 256, 0, s>>>(maps, G, out);
-    else if (vec == 4)
-        k_combine<4><<<blocks_for((G + 3) / 4, 256), 256, 0, s>>>(maps, G, out);
+hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, hipStream_t s) {
+    if (G >= 16)  // two 16-byte chunks per lane
+        k_combine<16><<<blocks_for(((G + 15) / 16 + 1) / 2, 256), 256, 0, s>>>(maps, G, out);
     else
         k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(maps, G, out);
     return hipGetLastError();
 }
 
 hipError_t launch_range_level(const uint8_t* src, int64_t h, uint8_t* dst, int64_t count, int64_t G,
-                              int vec, hipStream_t s) {
+                              hipStream_t s) {
     const int64_t total = count * G;
-    if (vec == 16) {
-        const int64_t blocks = (total / 16 + 255) / 256;
+    if (total >= 16) {
+        const int64_t blocks = ((total + 15) / 16 + 255) / 256;
         if (blocks > INT32_MAX) return hipErrorInvalidValue;
         k_range_level<16><<<(unsigned)blocks, 256, 0, s>>>(src, h, dst, total, G);
     } else {
@@ -1634,8 +1660,10 @@ hipError_t launch_range_level(const uint8_t* src, int64_t h, uint8_t* dst, int64
 hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
     int64_t blocks = 0;
     for (int k = 0; k < a.count; ++k) {
+        const int64_t G = a.it[k].G;
         a.it[k].first_block = blocks;
-        blocks += ((a.it[k].G + 15) / 16 + 255) / 256;
+        a.it[k].blocks = G >= 16 ? (((G + 15) / 16 + 1) / 2 + 255) / 256 : 1;
+        blocks += a.it[k].blocks;
     }
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     k_batch_combine<<<(unsigned)blocks, 256, 0, s>>>(a);

@@ -38,9 +38,8 @@ struct BatchItem {
     uint8_t* out;
     int64_t G;
     int64_t first_block;  // first work-group of this volume (set by the launcher)
+    int64_t blocks;       // work-groups of this volume (set by the launcher)
     uint64_t mask[4];     // active partitions
-    int32_t vec16;        // G % 16 == 0 and both pointers 16-byte aligned
-    int32_t pad;
 };
 
 struct BatchArgs {
@@ -126,10 +125,12 @@ hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vol
                               BatchSync* d_sync, const int64_t totals[3], int lines_mult,
                               int single, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
-hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, int vec, hipStream_t s);
+// out = element-wise min of the listed maps of G bytes (255 for none); any
+// size and pointer alignment.
+hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, hipStream_t s);
 // dst[p] = min(src[p], src[p + h]) for maps p = 0..count-1 (maps of G bytes,
 // contiguous): one level of the range table from the level below.
 hipError_t launch_range_level(const uint8_t* src, int64_t h, uint8_t* dst, int64_t count, int64_t G,
-                              int vec, hipStream_t s);
+                              hipStream_t s);
 
 }  // namespace pdm

@@ -126,6 +126,35 @@ def test_active_set_matches_oracle(orc):
     np.testing.assert_array_equal(L.active_set(bounds, a, 256), orc.active(bounds, a, 256))
     assert L.mask_to_list(L.active_set(bounds, a, 256), 32) == \
         orc.active_list(orc.active(bounds, a, 256), 32)
+    # -0 is zero (its partition stays out); a subnormal and a NaN in the last
+    # entry of a partition are non-zero; 4096 levels in 64 partitions
+    bounds = W.uniform_bounds(4096, 64)
+    a = np.zeros(4096, np.float32)
+    a[0:64] = -0.0
+    a[64 + 17] = np.float32(1e-42)
+    a[2 * 64 - 1] = np.nan
+    a[4095] = np.float32(-1e-45)
+    m = L.active_set(bounds, a, 4096)
+    np.testing.assert_array_equal(m, orc.active(bounds, a, 4096))
+    assert L.mask_to_list(m, 64) == [1, 63]
+
+
+def test_opacity_table_marshalling():
+    a = np.linspace(0, 1, 256, dtype=np.float32)
+    b, p = L._opacity_table(a, 256, "alpha")
+    assert b is a and p == a.ctypes.data
+    ro = a.copy()
+    ro.flags.writeable = False
+    b, p = L._opacity_table(ro, 256, "alpha")
+    assert b is ro and p == ro.ctypes.data
+    b, p = L._opacity_table(a.astype(np.float64), 256, "alpha")   # converted copy
+    assert b.dtype == np.float32 and p == b.ctypes.data
+    np.testing.assert_array_equal(b, a)
+    wide = np.zeros((256, 2), np.float32)
+    b, p = L._opacity_table(wide[:, 0], 256, "alpha")             # strided: copied
+    assert b.flags.c_contiguous and p == b.ctypes.data
+    with pytest.raises(ValueError):
+        L._opacity_table(a[:255], 256, "alpha")
 
 
 def test_binding_rejects_wrong_alpha_length():

@@ -396,6 +396,81 @@ def test_batch_tf_update_matches_oracle(pdm, orc):
         assert torch.equal(o, out)
 
 
+def _at_offset(t, off):
+    """A copy of the uint8 device tensor `t` that starts `off` bytes into a
+    larger buffer (a contiguous tensor whose base is not 16-byte aligned)."""
+    import torch
+    flat = t.reshape(-1)
+    buf = torch.full((flat.numel() + off + 5,), 77, dtype=torch.uint8, device=t.device)
+    view = buf[off:off + flat.numel()]
+    view.copy_(flat)
+    return buf, view
+
+
+# G = 1, 15, 16, 17, 62 and 924 bricks (the chunk-per-lane path with its
+# overlapping last chunk, and the byte path below 16 bricks)
+COMBINE_SHAPES = [(1, 1, 1), (4, 4, 60), (4, 4, 64), (4, 4, 68), (4, 8, 124), (43, 27, 45)]
+
+
+def test_combine_any_size_and_alignment(pdm, orc):
+    """Every combine path (single update, update through range tables, range
+    table levels, batched update) at sizes around the 16-byte chunk and with
+    PDMs, tables and outputs at odd byte offsets, against the oracle."""
+    import torch
+    rng = np.random.default_rng(71)
+    L, n, K = 256, 12, 3
+    bounds = W.uniform_bounds(L, n)
+    batch, wants = [], []
+    for k, shape in enumerate(COMBINE_SHAPES):
+        vol = blocky(shape, np.uint8, L, seed=300 + k, keep=0.4, cell=1)
+        v = pdm.Volume(pdm.to_device(vol), L, bounds)
+        v.build()
+        G = v.G
+        pd_stack = orc.pdms(vol, bounds, L)
+        np.testing.assert_array_equal(pdm.from_device(v.pdms).reshape(pd_stack.shape), pd_stack)
+        _, pdms_odd = _at_offset(v.pdms, 3 + k)
+        maps = pdm.range_table_maps(n, K)
+        tbuf = torch.full((maps * G + 7 + k,), 9, dtype=torch.uint8, device="cuda")
+        table = tbuf[1 + k:1 + k + maps * G]
+        say(f"[case] combine G={G} shape={shape}")
+        pdm.build_range_table(v.desc, pdms_odd, n, K, table)
+        want_table = orc.range_table(pd_stack, K)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pdm.from_device(table).reshape(want_table.shape), want_table,
+                                      err_msg=f"range table G={G}")
+        for j in range(3):
+            alpha = W.trapezoid_tf(L, int(rng.integers(1, 4)), rng)
+            if j == 2:
+                alpha = np.zeros(L, np.float32)   # empty S: 255 everywhere
+            want, wm = orc.tf_update(pd_stack, bounds, alpha, L)
+            obuf = torch.full((G + 9,), 5, dtype=torch.uint8, device="cuda")
+            out = obuf[1 + j + k % 3:1 + j + k % 3 + G]
+            m = pdm.tf_update(v.desc, pdms_odd, bounds, alpha, out)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(m, wm)
+            np.testing.assert_array_equal(pdm.from_device(out).reshape(want.shape), want,
+                                          err_msg=f"tf_update G={G} tf {j}")
+            out.fill_(3)
+            pdm.tf_update_ranges(v.desc, pdms_odd, table, bounds, K, alpha, out)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(pdm.from_device(out).reshape(want.shape), want,
+                                          err_msg=f"tf_update_ranges G={G} tf {j}")
+            # bytes around the output untouched
+            lo = 1 + j + k % 3
+            assert int(obuf[:lo].min()) == 5 and int(obuf[lo + G:].max()) == 5
+        alpha = W.trapezoid_tf(L, 2, rng)
+        ob, out = _at_offset(torch.zeros(G, dtype=torch.uint8, device="cuda"), 1 + 2 * k)
+        batch.append((v, pdms_odd, alpha, out))
+        wants.append(orc.tf_update(pd_stack, bounds, alpha, L))
+    say("[case] batched combine over all sizes at odd offsets")
+    masks = pdm.batch_tf_update([(v.desc, p, bounds, a, o) for v, p, a, o in batch])
+    torch.cuda.synchronize()
+    for k, ((v, _, _, out), (want, wm)) in enumerate(zip(batch, wants)):
+        np.testing.assert_array_equal(masks[k], wm)
+        np.testing.assert_array_equal(pdm.from_device(out).reshape(want.shape), want,
+                                      err_msg=f"batched G={v.G}")
+
+
 # ------------------------------------------------------ batched build
 @pytest.mark.parametrize("config", [None, dict(rows_per_item=1, lines_mult=4, largest_first=1),
                                     dict(rows_per_item=7, lines_mult=1),
