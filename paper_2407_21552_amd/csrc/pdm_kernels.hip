@@ -1044,14 +1044,16 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
 // starts at min(16c, G - 16), so the last chunk ends at G and overlaps its
 // neighbour, whose lane writes the same bytes there.  Chunks are loaded and
 // stored at any byte alignment (the hardware serves unaligned vector
-// accesses), so every size and every base pointer take this path; maps of
-// fewer than 16 bytes take a byte path (VEC = 1).
-// Each lane owns two chunks, `nthr` chunks apart so that every load
-// instruction of a wave covers 1 KiB of one stream; maps are taken two at a
-// time, so four 16-byte non-temporal loads are in flight per lane (the maps
-// are streamed once per update and do not fit in the caches).  The running
-// minimum is kept as even/odd byte pairs in packed u16 lanes.  An empty list
-// writes 255.
+// accesses), so every size and every base pointer take the chunked path.
+// CHUNKS = chunks per lane:
+//   2  large maps: chunks t and t + nthr, maps two at a time (four 16-byte
+//      non-temporal loads in flight; every load instruction of a wave covers
+//      1 KiB of one stream).  Measured best on runs of consecutive PDMs.
+//   1  small maps (too few chunks to give every CU several work-groups with
+//      two per lane): one chunk per lane, maps four at a time.
+//   0  maps of fewer than 16 bytes: one byte per lane.
+// The running minimum is kept as even/odd byte pairs in packed u16 lanes.
+// An empty list writes 255.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void min_bytes16(uint32_t (&e)[4], uint32_t (&o)[4], const u32x4 w) {
     e[0] = pk_min16(e[0], even_bytes(w.x));
@@ -1072,43 +1074,33 @@ __device__ __forceinline__ void store16_u(PDM_GLB uint8_t* p, const u32x4 v) {
     *reinterpret_cast<PDM_GLB u32x4_u*>(p) = v;
 }
 
-// Minimum of the chunks at o0 and o1 over the maps added so far.
-struct ChunkMin2 {
-    uint32_t e0[4], d0[4], e1[4], d1[4];
+typedef const PDM_GLB uint8_t* MapPtr;
 
-    __device__ __forceinline__ ChunkMin2() {
+// Minimum of one 16-byte chunk over the maps added so far.
+struct ChunkMin {
+    uint32_t e[4], o[4];
+
+    __device__ __forceinline__ ChunkMin() {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e0[k] = d0[k] = e1[k] = d1[k] = 0x00FF00FFu;
+        for (int k = 0; k < 4; ++k) e[k] = o[k] = 0x00FF00FFu;
     }
-    __device__ __forceinline__ void add(const PDM_GLB uint8_t* a, int64_t o0, int64_t o1) {
-        const u32x4 a0 = load16_nt(a + o0), a1 = load16_nt(a + o1);
-        min_bytes16(e0, d0, a0);
-        min_bytes16(e1, d1, a1);
+    __device__ __forceinline__ void add(const u32x4 w) { min_bytes16(e, o, w); }
+    // N maps: every load issued before the first minimum
+    template <int N>
+    __device__ __forceinline__ void add(const MapPtr (&m)[N], int64_t off) {
+        u32x4 w[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) w[i] = load16_nt(m[i] + off);
+#pragma unroll
+        for (int i = 0; i < N; ++i) min_bytes16(e, o, w[i]);
     }
-    // two maps: all four loads issued before the first minimum
-    __device__ __forceinline__ void add2(const PDM_GLB uint8_t* a, const PDM_GLB uint8_t* b,
-                                         int64_t o0, int64_t o1) {
-        const u32x4 a0 = load16_nt(a + o0), a1 = load16_nt(a + o1);
-        const u32x4 b0 = load16_nt(b + o0), b1 = load16_nt(b + o1);
-        min_bytes16(e0, d0, a0);
-        min_bytes16(e1, d1, a1);
-        min_bytes16(e0, d0, b0);
-        min_bytes16(e1, d1, b1);
-    }
-    __device__ __forceinline__ void store(PDM_GLB uint8_t* out, int64_t o0, int64_t o1, bool two) const {
+    __device__ __forceinline__ void store(PDM_GLB uint8_t* out, int64_t off) const {
         u32x4 r;
-        r.x = e0[0] | (d0[0] << 8);
-        r.y = e0[1] | (d0[1] << 8);
-        r.z = e0[2] | (d0[2] << 8);
-        r.w = e0[3] | (d0[3] << 8);
-        store16_u(out + o0, r);
-        if (two) {
-            r.x = e1[0] | (d1[0] << 8);
-            r.y = e1[1] | (d1[1] << 8);
-            r.z = e1[2] | (d1[2] << 8);
-            r.w = e1[3] | (d1[3] << 8);
-            store16_u(out + o1, r);
-        }
+        r.x = e[0] | (o[0] << 8);
+        r.y = e[1] | (o[1] << 8);
+        r.z = e[2] | (o[2] << 8);
+        r.w = e[3] | (o[3] << 8);
+        store16_u(out + off, r);
     }
 };
 
@@ -1121,22 +1113,57 @@ __device__ __forceinline__ PDM_GLB T* glb(T* p) {
     return (PDM_GLB T*)p;
 }
 
-template <int VEC>
+template <int CHUNKS>
 __global__ void __launch_bounds__(256) k_combine(MapList maps, int64_t G, uint8_t* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = maps.count;
-    if constexpr (VEC == 16) {
+    if constexpr (CHUNKS == 2) {
         const int64_t nch = (G + 15) / 16;
         const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
         const int64_t i0 = t, i1 = t + nthr;
         if (i0 >= nch) return;
         const bool two = i1 < nch;
         const int64_t o0 = chunk_off(i0, G), o1 = two ? chunk_off(i1, G) : o0;
-        ChunkMin2 acc;
+        ChunkMin c0, c1;
         int j = 0;
-        for (; j + 2 <= cnt; j += 2) acc.add2(glb(maps.src[j]), glb(maps.src[j + 1]), o0, o1);
-        if (j < cnt) acc.add(glb(maps.src[j]), o0, o1);
-        acc.store(glb(out), o0, o1, two);
+        for (; j + 2 <= cnt; j += 2) {
+            const MapPtr pa = glb(maps.src[j]), pb = glb(maps.src[j + 1]);
+            const u32x4 a0 = load16_nt(pa + o0), a1 = load16_nt(pa + o1);
+            const u32x4 b0 = load16_nt(pb + o0), b1 = load16_nt(pb + o1);
+            c0.add(a0);
+            c1.add(a1);
+            c0.add(b0);
+            c1.add(b1);
+        }
+        if (j < cnt) {
+            const MapPtr pa = glb(maps.src[j]);
+            const u32x4 a0 = load16_nt(pa + o0), a1 = load16_nt(pa + o1);
+            c0.add(a0);
+            c1.add(a1);
+        }
+        c0.store(glb(out), o0);
+        if (two) c1.store(glb(out), o1);
+    } else if constexpr (CHUNKS == 1) {
+        if (t >= (G + 15) / 16) return;
+        const int64_t off = chunk_off(t, G);
+        ChunkMin acc;
+        int j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            const MapPtr m[4] = {glb(maps.src[j]), glb(maps.src[j + 1]), glb(maps.src[j + 2]),
+                                 glb(maps.src[j + 3])};
+            acc.add(m, off);
+        }
+        if (cnt - j == 3) {
+            const MapPtr m[3] = {glb(maps.src[j]), glb(maps.src[j + 1]), glb(maps.src[j + 2])};
+            acc.add(m, off);
+        } else if (cnt - j == 2) {
+            const MapPtr m[2] = {glb(maps.src[j]), glb(maps.src[j + 1])};
+            acc.add(m, off);
+        } else if (cnt - j == 1) {
+            const MapPtr m[1] = {glb(maps.src[j])};
+            acc.add(m, off);
+        }
+        acc.store(glb(out), off);
     } else {
         if (t >= G) return;
         uint32_t m = 255u;
@@ -1159,10 +1186,10 @@ __global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__
     if constexpr (VEC == 16) {
         if (t >= (total + 15) / 16) return;
         const int64_t off = chunk_off(t, total);
-        const PDM_GLB uint8_t* s = glb(src);
-        ChunkMin2 acc;
-        acc.add2(s + off, s + off + h * G, 0, 0);
-        acc.store(glb(dst), off, off, false);
+        const MapPtr m[2] = {glb(src), glb(src) + h * G};
+        ChunkMin acc;
+        acc.add(m, off);
+        acc.store(glb(dst), off);
     } else {
         if (t >= total) return;
         dst[t] = (uint8_t)umin((uint32_t)src[t], (uint32_t)src[t + h * G]);
@@ -1174,9 +1201,10 @@ __global__ void __launch_bounds__(256) k_range_level(const uint8_t* __restrict__
 // has its own PDM stack, output map and active set (a 256-bit mask); blocks
 // are assigned to volumes by the prefix counts in first_block (a binary
 // search), so every work-group serves one volume and its control values are
-// uniform.  Within a volume the work is that of k_combine: two 16-byte chunks
-// per lane at any size and alignment, the active PDMs taken two at a time;
-// volumes of fewer than 16 bricks take a byte path.
+// uniform.  Within a volume the work is that of k_combine for small maps
+// (batched volumes are mostly small): one 16-byte chunk per lane at any size
+// and alignment, the active PDMs taken four at a time; volumes of fewer than
+// 16 bricks take a byte path.
 // ---------------------------------------------------------------------------
 // The set bits of a 256-bit mask in increasing order: the current word and
 // its index are kept (in scalar registers: the mask is uniform), the next
@@ -1213,24 +1241,35 @@ __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
     const int64_t t = ((int64_t)blockIdx.x - it.first_block) * blockDim.x + threadIdx.x;
     BitWalk bits(it.mask);
     if (G >= 16) {
-        const int64_t nch = (G + 15) / 16;
-        const int64_t nthr = it.blocks * (int64_t)blockDim.x;
-        const int64_t i0 = t, i1 = t + nthr;
-        if (i0 >= nch) return;
-        const bool two = i1 < nch;
-        const int64_t o0 = chunk_off(i0, G), o1 = two ? chunk_off(i1, G) : o0;
-        ChunkMin2 acc;
-        for (;;) {
-            const int pa = bits.next();
-            if (pa < 0) break;
-            const int pb = bits.next();
-            if (pb < 0) {
-                acc.add(pdms + (int64_t)pa * G, o0, o1);
-                break;
+        if (t >= (G + 15) / 16) return;
+        const int64_t off = chunk_off(t, G);
+        ChunkMin acc;
+        for (;;) {  // four active PDMs per step, then the last one to three
+            const int p0 = bits.next();
+            if (p0 < 0) break;
+            const int p1 = bits.next();
+            const int p2 = p1 < 0 ? -1 : bits.next();
+            const int p3 = p2 < 0 ? -1 : bits.next();
+            if (p3 >= 0) {
+                const MapPtr m[4] = {pdms + (int64_t)p0 * G, pdms + (int64_t)p1 * G,
+                                     pdms + (int64_t)p2 * G, pdms + (int64_t)p3 * G};
+                acc.add(m, off);
+                continue;
             }
-            acc.add2(pdms + (int64_t)pa * G, pdms + (int64_t)pb * G, o0, o1);
+            if (p2 >= 0) {
+                const MapPtr m[3] = {pdms + (int64_t)p0 * G, pdms + (int64_t)p1 * G,
+                                     pdms + (int64_t)p2 * G};
+                acc.add(m, off);
+            } else if (p1 >= 0) {
+                const MapPtr m[2] = {pdms + (int64_t)p0 * G, pdms + (int64_t)p1 * G};
+                acc.add(m, off);
+            } else {
+                const MapPtr m[1] = {pdms + (int64_t)p0 * G};
+                acc.add(m, off);
+            }
+            break;
         }
-        acc.store(out, o0, o1, two);
+        acc.store(out, off);
     } else {
         if (t >= G) return;
         uint32_t v = 255u;
@@ -1634,11 +1673,18 @@ hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, 
     return hipSuccess;
 }
 
+// Two chunks per lane from this many chunks on: 256 CUs x 4 work-groups of
+// 256 lanes x 2 chunks (maps of 8 MiB and more).
+constexpr int64_t kCombineWideChunks = 256LL * 4 * 256 * 2;
+
 hipError_t launch_combine(const MapList& maps, int64_t G, uint8_t* out, hipStream_t s) {
-    if (G >= 16)  // two 16-byte chunks per lane
-        k_combine<16><<<blocks_for(((G + 15) / 16 + 1) / 2, 256), 256, 0, s>>>(maps, G, out);
+    const int64_t nch = (G + 15) / 16;
+    if (G < 16)
+        k_combine<0><<<blocks_for(G, 256), 256, 0, s>>>(maps, G, out);
+    else if (nch >= kCombineWideChunks)
+        k_combine<2><<<blocks_for((nch + 1) / 2, 256), 256, 0, s>>>(maps, G, out);
     else
-        k_combine<1><<<blocks_for(G, 256), 256, 0, s>>>(maps, G, out);
+        k_combine<1><<<blocks_for(nch, 256), 256, 0, s>>>(maps, G, out);
     return hipGetLastError();
 }
 
@@ -1662,7 +1708,7 @@ hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
     for (int k = 0; k < a.count; ++k) {
         const int64_t G = a.it[k].G;
         a.it[k].first_block = blocks;
-        a.it[k].blocks = G >= 16 ? (((G + 15) / 16 + 1) / 2 + 255) / 256 : 1;
+        a.it[k].blocks = G >= 16 ? ((G + 15) / 16 + 255) / 256 : 1;
         blocks += a.it[k].blocks;
     }
     if (blocks > INT32_MAX) return hipErrorInvalidValue;

@@ -471,6 +471,47 @@ def test_combine_any_size_and_alignment(pdm, orc):
                                       err_msg=f"batched G={v.G}")
 
 
+def test_combine_wide_ragged_unaligned(pdm, orc):
+    """The two-chunks-per-lane combine (maps of 8 MiB and more) at a size that
+    is not a multiple of 16 (G = 203*203*205 = 8,447,845) with the PDMs, the
+    range table and the output at odd byte offsets; the maps are random bytes
+    (the combine takes any maps), D' against the oracle's Eq. 1."""
+    import torch
+    from paper_2407_21552_amd import _lib
+    rng = np.random.default_rng(88)
+    L, n, K = 256, 16, 2
+    desc = _lib.VolumeDesc(nx=812, ny=812, nz=820, dtype=1, levels=L, brick=4)
+    G = pdm.grid_of(desc)[3]
+    assert G == 203 * 203 * 205 and G % 16 == 5
+    stack = rng.integers(0, 256, size=(n, G), dtype=np.uint8)
+    _, pdms = _at_offset(pdm.to_device(stack), 7)
+    maps = pdm.range_table_maps(n, K)
+    tbuf = torch.empty(maps * G + 16, dtype=torch.uint8, device="cuda")
+    table = tbuf[3:3 + maps * G]
+    bounds = W.uniform_bounds(L, n)
+    say(f"[case] wide combine G={G}")
+    pdm.build_range_table(desc, pdms, n, K, table)
+    want_table = orc.range_table(stack, K)
+    torch.cuda.synchronize()
+    assert torch.equal(table.cpu(), torch.from_numpy(want_table.reshape(-1)))
+    del want_table
+    obuf = torch.full((G + 20,), 5, dtype=torch.uint8, device="cuda")
+    out = obuf[9:9 + G]
+    for j in range(4):
+        alpha = W.trapezoid_tf(L, j + 1, rng) if j < 3 else np.ones(L, np.float32)
+        want, wm = orc.tf_update(stack, bounds, alpha, L)
+        out.fill_(1)
+        m = pdm.tf_update(desc, pdms, bounds, alpha, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(m, wm)
+        assert torch.equal(out.cpu(), torch.from_numpy(want.reshape(-1))), f"tf_update tf {j}"
+        out.fill_(2)
+        pdm.tf_update_ranges(desc, pdms, table, bounds, K, alpha, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out.cpu(), torch.from_numpy(want.reshape(-1))), f"ranges tf {j}"
+        assert int(obuf[:9].min()) == 5 and int(obuf[9 + G:].max()) == 5
+
+
 # ------------------------------------------------------ batched build
 @pytest.mark.parametrize("config", [None, dict(rows_per_item=1, lines_mult=4, largest_first=1),
                                     dict(rows_per_item=7, lines_mult=1),
