@@ -25,7 +25,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
 volumes (22 of the batched recipe and two 1024x1024x795 tube trees) served
 with continuous batching; p50/p99 latency and updates/s, beside the same
 schedule through a serial full-recompute queue (service times measured per
-volume on the GPU).
+volume on the GPU).  Then short load levels (--serve-load-rates) on the warm
+servers, where batches form: achieved updates/s, mean batch, p50/p99.
 
 --workload sweep: partition counts 16..256, uniform and with a partition of
 its own for rho_min, on the CT-like u16 volume, the tube tree and an
@@ -199,6 +200,9 @@ def main():
                          "beside the plain update)")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-load-rates", default="20000,60000,150000",
+                    help="comma-separated request rates of the served load levels")
+    ap.add_argument("--serve-load-seconds", type=float, default=2.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -551,6 +555,17 @@ def run_served(args):
                             lambda k=k: host[k])
     arrivals = W.poisson_requests(args.serve_rate, args.serve_seconds, list(cat),
                                   {k: cat[k].levels for k in cat}, seed=12)
+    rates = [float(r) for r in args.serve_load_rates.split(",") if r.strip()]
+
+    def serve_on(srv, arr, seconds):
+        # one stream on a warm server: counters and results start afresh
+        srv.completed, srv.rejected = [], []
+        srv.stats.clear()
+        sched = requests_from(arr)
+        srv.t0 = srv.clock()
+        srv.run(sched, timeout=seconds + 60)
+        torch.cuda.synchronize()
+        return sched, srv.report()
 
     def serve(range_level):
         ex = GpuExecutor(outputs_per_volume=8, range_level=range_level)
@@ -561,17 +576,21 @@ def run_served(args):
         torch.cuda.synchronize()
         for h in srv.resident.values():
             ex.ready(h)
-        sched = requests_from(arrivals)
-        log(f"serving {len(sched)} requests over {args.serve_seconds:.0f} s ...")
-        srv.t0 = srv.clock()
-        srv.run(sched, timeout=args.serve_seconds + 60)
-        torch.cuda.synchronize()
-        return srv, sched, srv.report()
+        log(f"serving {len(arrivals)} requests over {args.serve_seconds:.0f} s ...")
+        sched, rep = serve_on(srv, arrivals, args.serve_seconds)
+        load = []
+        for k, rate in enumerate(rates):
+            arr = W.poisson_requests(rate, args.serve_load_seconds, list(cat),
+                                     {v: cat[v].levels for v in cat}, seed=40 + k, tf_pool=16)
+            log(f"load {rate:.0f}/s: {len(arr)} requests over {args.serve_load_seconds:.1f} s ...")
+            _, r = serve_on(srv, arr, args.serve_load_seconds)
+            load.append({"rate_hz": rate, **r})
+        return srv, sched, rep, load
 
-    srv_rt, _, rep_rt = serve(args.range_level)
+    srv_rt, _, rep_rt, load_rt = serve(args.range_level)
     del srv_rt
     torch.cuda.empty_cache()
-    srv, sched, rep = serve(None)
+    srv, sched, rep, load = serve(None)
 
     # per-volume service times of the plain method and of a single update
     log("measuring per-volume full recompute and single update times ...")
@@ -608,6 +627,8 @@ def run_served(args):
                    "requests": len(sched), "rate_hz": args.serve_rate},
         "served": rep,
         "served_range_tables": {**rep_rt, "range_level": args.range_level},
+        "load": {"seconds": args.serve_load_seconds, "tfs_per_volume": 16,
+                 "batched": load, "range_tables": load_rt},
         "serial_full_recompute": serial_queue(sched, full_s),
         "serial_single_update": serial_queue(sched, upd_s),
         "service_ms_mean": {"full_recompute": round(1e3 * float(np.mean(list(full_s.values()))), 4),

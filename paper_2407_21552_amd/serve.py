@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import itertools
 import time
 from typing import Callable, Dict, List, Optional
 
@@ -75,6 +76,11 @@ class Executor:
     def evict(self, handle) -> None:
         raise NotImplementedError
 
+    def per_volume_limit(self) -> Optional[int]:
+        """Most requests of one volume that one launch may hold (None: no
+        limit)."""
+        return None
+
     def launch(self, batch: List[tuple]):
         """batch: list of (handle, alpha, request).  Start one batched update;
         returns a ticket."""
@@ -96,7 +102,8 @@ class Server:
         self.t0 = clock()
         self.resident: "collections.OrderedDict[int, object]" = collections.OrderedDict()  # LRU order
         self.used = 0
-        self.queue: List[Request] = []
+        self.queue: "collections.deque[Request]" = collections.deque()
+        self._skipped: List[Request] = []  # taken off the queue by the running tick
         self.inflight: List[tuple] = []   # (ticket, [requests])
         self.busy: Dict[int, int] = collections.Counter()  # vol_id -> requests in flight
         self.completed: List[Request] = []
@@ -111,7 +118,8 @@ class Server:
         """Evict LRU idle volumes until `need` bytes and a slot are free."""
         while (self.used + need > self.budget or len(self.resident) >= self.max_slots):
             victim = next((v for v in self.resident if self.busy[v] == 0
-                           and not any(r.vol_id == v for r in self.queue)), None)
+                           and not any(r.vol_id == v
+                                       for r in itertools.chain(self.queue, self._skipped))), None)
             if victim is None:
                 victim = next((v for v in self.resident if self.busy[v] == 0), None)
             if victim is None:
@@ -166,25 +174,34 @@ class Server:
 
     def tick(self) -> int:
         """Retire finished launches, admit volumes for queued requests, and
-        launch one batch of ready requests.  Returns the batch size."""
+        launch one batch of ready requests, taken in arrival order.  The scan
+        stops once the batch is full, so a long queue costs no more per tick
+        than the requests it skips (volume not ready, or its per-launch
+        limit reached).  Returns the batch size."""
         self._retire()
-        batch, rest = [], []
-        for r in self.queue:
-            if len(batch) >= self.max_batch:
-                rest.append(r)
+        batch, skipped = [], self._skipped
+        per_vol = collections.Counter()
+        limit = self.ex.per_volume_limit()
+        q = self.queue
+        while q and len(batch) < self.max_batch:
+            r = q.popleft()
+            if limit is not None and per_vol[r.vol_id] >= limit:
+                skipped.append(r)
                 continue
             h = self._ensure(r.vol_id)
             if h is None:
                 r.error = "volume larger than the memory budget"
                 self.rejected.append(r)
             elif isinstance(h, str) or not self.ex.ready(h):
-                rest.append(r)
+                skipped.append(r)
             else:
                 # counted busy at once, so a later admission in this tick
                 # cannot evict this volume
                 self.busy[r.vol_id] += 1
+                per_vol[r.vol_id] += 1
                 batch.append((h, r.alpha, r))
-        self.queue = rest
+        q.extendleft(reversed(skipped))
+        skipped.clear()
         if batch:
             self.inflight.append((self.ex.launch(batch), [r for _, _, r in batch]))
             self.stats["launches"] += 1
@@ -249,8 +266,10 @@ class GpuExecutor(Executor):
     voxels and builds bricks and PDMs (and, with `range_level`, the range
     table) on `admit_stream`; updates run on `update_stream`, one batched
     launch per tick (with `range_level`: one update through the table per
-    request); each request gets its own output map from a per-volume pool of
-    `outputs_per_volume` buffers."""
+    request).  Each request gets an output map from a per-volume pool of
+    `outputs_per_volume` buffers, used in turn: a result stays valid until
+    that many later requests of the same volume have been launched, and one
+    launch holds at most that many requests of a volume."""
 
     def __init__(self, outputs_per_volume: int = 8, keep_volume: bool = False,
                  range_level: Optional[int] = None):
@@ -314,6 +333,9 @@ class GpuExecutor(Executor):
     def evict(self, h) -> None:
         h.vol = None
         h.outs = None
+
+    def per_volume_limit(self) -> Optional[int]:
+        return self.outputs
 
     def launch(self, batch):
         import paper_2407_21552_amd as pdm

@@ -2,6 +2,8 @@
 computes through the oracle: admission by memory budget and slot cap, LRU
 eviction of idle volumes, rejection of bad requests, continuous batching of
 requests that arrive while launches are in flight, and exact results."""
+import collections
+
 import numpy as np
 import pytest
 
@@ -157,3 +159,63 @@ def test_max_batch_and_poisson_schedule(orc):
     assert len(srv.completed) == len(sched)
     rep = srv.report()
     assert rep["completed"] == len(sched) and rep["p99_ms"] >= rep["p50_ms"]
+
+
+class LimitedExecutor(OracleExecutor):
+    """An executor whose launches hold at most `limit` requests of a volume
+    (as the GPU executor's pool of output maps)."""
+
+    def __init__(self, orc, limit):
+        super().__init__(orc)
+        self.limit = limit
+
+    def per_volume_limit(self):
+        return self.limit
+
+
+def test_per_volume_limit_keeps_arrival_order(orc):
+    cat = catalog(3)
+    ex = LimitedExecutor(orc, limit=2)
+    srv = Server(ex, cat, budget_bytes=10**9, max_batch=8)
+    rng = np.random.default_rng(6)
+    vols = [0, 0, 0, 1, 0, 2, 1, 1, 1, 0]
+    for i, (v, a) in enumerate(zip(vols, tfs(rng, len(vols)))):
+        srv.submit(Request(i, v, a, 0.0))
+    srv.drain()
+    assert len(srv.completed) == len(vols)
+    for launch in ex.launches:
+        per = collections.Counter(vols[i] for i in launch)
+        assert max(per.values()) <= 2
+    # each launch takes the earliest requests its limits allow, in order
+    assert ex.launches[0] == [0, 1, 3, 5, 6]
+    assert sorted(i for b in ex.launches for i in b) == list(range(len(vols)))
+    for b in ex.launches:
+        assert b == sorted(b)
+    for r in srv.completed:
+        spec = cat[r.vol_id]
+        want = orc.tf_update(orc.pdms(spec.load(), spec.bounds, 256), spec.bounds, r.alpha, 256)[0]
+        np.testing.assert_array_equal(r.result, want)
+
+
+def test_long_queue_drains_in_arrival_order(orc):
+    cat = catalog(2)
+    ex = OracleExecutor(orc)
+    srv = Server(ex, cat, budget_bytes=10**9, max_batch=16)
+    rng = np.random.default_rng(8)
+    a = tfs(rng, 4)
+    n = 2000
+    for i in range(n):
+        srv.submit(Request(i, i % 2, a[i % 4], 0.0))
+    srv.drain()
+    assert len(srv.completed) == n and len(ex.launches) == n // 16
+    assert [i for b in ex.launches for i in b] == list(range(n))
+
+
+def test_pooled_poisson_tfs_are_shared():
+    sched = W.poisson_requests(5000.0, 0.2, [0, 1], {0: 256, 1: 4096}, seed=3, tf_pool=4)
+    assert len(sched) > 500
+    ids = collections.defaultdict(set)
+    for _, v, alpha in sched:
+        assert alpha.shape == ({0: 256, 1: 4096}[v],)
+        ids[v].add(id(alpha))
+    assert all(len(s) <= 4 for s in ids.values())

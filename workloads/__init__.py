@@ -371,20 +371,31 @@ def make_tfs(name: str, count=None):
     return out
 
 
-def poisson_requests(rate_hz: float, seconds: float, vol_ids, levels_of, ramps=(1, 4), seed: int = 5):
+def poisson_requests(rate_hz: float, seconds: float, vol_ids, levels_of, ramps=(1, 4), seed: int = 5,
+                     tf_pool: int = 0):
     """A Poisson stream of TF-change requests: exponential inter-arrival gaps
     of mean 1/rate_hz over [0, seconds), each with a uniformly random volume id
-    and a random trapezoid TF of U{ramps} ramps.  Returns a list of
+    and a random trapezoid TF of U{ramps} ramps.  With `tf_pool` > 0 each
+    volume draws its TFs from a pool of that many (the arrays are shared, so
+    long high-rate streams stay small in host memory).  Returns a list of
     (arrival seconds, volume id, opacity table)."""
     rng = np.random.default_rng(seed)
     vol_ids = list(vol_ids)
+    pools = {}
+    if tf_pool > 0:
+        for v in vol_ids:
+            pools[v] = [trapezoid_tf(levels_of[v], int(rng.integers(ramps[0], ramps[1] + 1)), rng)
+                        for _ in range(tf_pool)]
     t, out = 0.0, []
     while True:
         t += rng.exponential(1.0 / rate_hz)
         if t >= seconds:
             break
         v = vol_ids[int(rng.integers(0, len(vol_ids)))]
-        alpha = trapezoid_tf(levels_of[v], int(rng.integers(ramps[0], ramps[1] + 1)), rng)
+        if tf_pool > 0:
+            alpha = pools[v][int(rng.integers(0, tf_pool))]
+        else:
+            alpha = trapezoid_tf(levels_of[v], int(rng.integers(ramps[0], ramps[1] + 1)), rng)
         out.append((t, v, alpha))
     return out
 
