@@ -192,6 +192,29 @@ typedef struct {
 pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
                                uint64_t* h_active, hipStream_t stream);
 
+/* Batched update through range tables: pdm_tf_update_ranges for up to
+ * PDM_BATCH_MAX requests (volume, TF, output), each reading the maps of its
+ * own cover, in one kernel launch; the same D' and S masks as the single
+ * calls.  The covers' map indices travel in the kernel arguments (room for
+ * 640); a batch whose covers hold more is split into several launches on
+ * `stream`, in order.  h_items: `count` descriptors (host, read during the
+ * call); every request is validated as in pdm_tf_update_ranges before
+ * anything is launched.  Outputs must not overlap.  h_active: nullable, 4
+ * words per item (the S masks, item-major). */
+typedef struct {
+    const pdm_volume* v;     /* geometry and levels of the volume */
+    const uint8_t* d_pdms;   /* n*G bytes */
+    const uint8_t* d_table;  /* the volume's range table (n, max_level); null when K = 0 */
+    const int32_t* h_bounds; /* n+1 partition borders */
+    int32_t n;               /* partitions */
+    int32_t max_level;       /* as given to pdm_build_range_table */
+    const float* h_alpha;    /* v->levels entries */
+    uint8_t* d_dist;         /* G bytes: D' */
+} pdm_batch_range_update;
+
+pdm_status pdm_batch_tf_update_ranges(const pdm_batch_range_update* h_items, int32_t count,
+                                      uint64_t* h_active, hipStream_t stream);
+
 /* Batched one-time initialisation: pdm_build_bricks + pdm_build_partitions
  * (Sec. 3.1: brick [min,max], then every partition's POM and its distance
  * transform) for up to PDM_BATCH_MAX volumes of different sizes, dtypes and

@@ -43,6 +43,13 @@ class BatchUpdate(ctypes.Structure):
                 ("h_alpha", ctypes.c_void_p), ("d_dist", ctypes.c_void_p)]
 
 
+class BatchRangeUpdate(ctypes.Structure):
+    _fields_ = [("v", ctypes.POINTER(VolumeDesc)), ("d_pdms", ctypes.c_void_p),
+                ("d_table", ctypes.c_void_p), ("h_bounds", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("h_alpha", ctypes.c_void_p), ("d_dist", ctypes.c_void_p)]
+
+
 BATCH_MAX = 48
 
 
@@ -90,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.pdm_full_recompute_exact.argtypes = [V, P, P, P, P]
         L.pdm_plain_exact_distance_x.argtypes = [V, P, P, P, P]
         L.pdm_batch_tf_update.argtypes = [ctypes.POINTER(BatchUpdate), i32, P, P]
+        L.pdm_batch_tf_update_ranges.argtypes = [ctypes.POINTER(BatchRangeUpdate), i32, P, P]
         L.pdm_batch_workspace_bytes.argtypes = [i32]
         L.pdm_batch_workspace_bytes.restype = ctypes.c_size_t
         L.pdm_batch_build.argtypes = [ctypes.POINTER(BatchVolume), i32, P, ctypes.c_size_t,
@@ -99,7 +107,8 @@ def lib() -> ctypes.CDLL:
                      "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
                      "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
                      "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build",
-                     "pdm_build_range_table", "pdm_range_cover", "pdm_tf_update_ranges"):
+                     "pdm_build_range_table", "pdm_range_cover", "pdm_tf_update_ranges",
+                     "pdm_batch_tf_update_ranges"):
             getattr(L, name).restype = st
         L.pdm_range_table_maps.argtypes = [i32, i32]
         L.pdm_range_table_maps.restype = ctypes.c_int64
@@ -403,6 +412,14 @@ _BATCH_PTRS = struct.Struct("<QQ")
 assert (BatchUpdate.v.offset, BatchUpdate.d_pdms.offset, BatchUpdate.h_bounds.offset,
         BatchUpdate.n.offset, BatchUpdate.h_alpha.offset, BatchUpdate.d_dist.offset,
         ctypes.sizeof(BatchUpdate)) == (0, 8, 16, 24, 32, 40, _BATCH_FIXED.size + _BATCH_PTRS.size)
+# the same for pdm_batch_range_update: descriptor, PDMs, table, borders, n,
+# max_level fixed; opacity table and output per launch
+_RANGE_FIXED = struct.Struct("<QQQQii")
+assert (BatchRangeUpdate.v.offset, BatchRangeUpdate.d_pdms.offset, BatchRangeUpdate.d_table.offset,
+        BatchRangeUpdate.h_bounds.offset, BatchRangeUpdate.n.offset, BatchRangeUpdate.max_level.offset,
+        BatchRangeUpdate.h_alpha.offset, BatchRangeUpdate.d_dist.offset,
+        ctypes.sizeof(BatchRangeUpdate)) == (0, 8, 16, 24, 32, 36, 40, 48,
+                                             _RANGE_FIXED.size + _BATCH_PTRS.size)
 _F32 = np.dtype(np.float32)
 
 
@@ -412,7 +429,7 @@ class PreparedVolume:
     opacity tables and output maps.  The PDM tensor must stay alive and
     unchanged in place while the object is used."""
     __slots__ = ("desc", "levels", "G", "n", "bounds", "pdms", "fixed", "packed", "table",
-                 "max_level", "table_ptr")
+                 "max_level", "table_ptr", "packed_ranges")
 
     def __init__(self, desc, pdms, bounds, table=None, max_level: int = 0):
         self.desc = desc
@@ -431,6 +448,8 @@ class PreparedVolume:
         maps = range_table_maps(self.n, self.max_level)
         self.table = table
         self.table_ptr = _dev_ptr(table, maps * self.G, "table") if maps > 0 else ctypes.c_void_p(0)
+        self.packed_ranges = _RANGE_FIXED.pack(self.fixed[0], self.fixed[1], self.table_ptr.value or 0,
+                                               self.fixed[2], self.n, self.max_level)
 
 
 def _opacity_table(alpha, levels: int, what: str):
@@ -482,6 +501,60 @@ def tf_update_ranges_prepared(pv, alpha, dist, stream=None) -> np.ndarray:
                                       ctypes.c_void_p(dist.data_ptr()), _np_ptr(m), _stream(stream)),
            "pdm_tf_update_ranges")
     return m
+
+
+def batch_tf_update_ranges(items, stream=None) -> np.ndarray:
+    """TF updates through range tables of several volumes in one launch (more
+    when the covers' map lists need it).  items: sequence of (desc, pdms,
+    table, bounds, max_level, alpha, dist); table may be None when the level
+    count is 0.  Returns the S masks, shape (count, 4)."""
+    count = len(items)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
+    arr = (BatchRangeUpdate * count)()
+    keep = []
+    for k, (desc, pdms, table, bounds, max_level, alpha, dist) in enumerate(items):
+        G = grid_of(desc)[3]
+        b = _bounds(bounds)
+        n = len(b) - 1
+        a = _alpha(alpha, desc.levels)
+        maps = range_table_maps(n, max_level)
+        keep += [desc, b, a]
+        arr[k].v = ctypes.pointer(desc)
+        arr[k].d_pdms = _dev_ptr(pdms, n * G, "pdms")
+        arr[k].d_table = _dev_ptr(table, maps * G, "table") if maps > 0 else None
+        arr[k].h_bounds = _np_ptr(b)
+        arr[k].n = n
+        arr[k].max_level = int(max_level)
+        arr[k].h_alpha = _np_ptr(a)
+        arr[k].d_dist = _dev_ptr(dist, G, "dist")
+    masks = np.zeros((count, 4), np.uint64)
+    _check(lib().pdm_batch_tf_update_ranges(arr, count, _np_ptr(masks), _stream(stream)),
+           "pdm_batch_tf_update_ranges")
+    del keep
+    return masks
+
+
+def batch_tf_update_ranges_prepared(entries, stream=None) -> np.ndarray:
+    """batch_tf_update_ranges over prepared volumes that hold range tables.
+    entries: sequence of (PreparedVolume, alpha, dist).  Returns the S masks,
+    shape (count, 4)."""
+    count = len(entries)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
+    rows, keep = [], []
+    for k, (pv, alpha, dist) in enumerate(entries):
+        a, ap = _opacity_table(alpha, pv.levels, f"alpha {k}")
+        keep.append(a)
+        if dist.nbytes != pv.G or not dist.is_cuda or not dist.is_contiguous():
+            raise ValueError(f"dist {k}: expected a contiguous device tensor of {pv.G} bytes")
+        rows.append(pv.packed_ranges + _BATCH_PTRS.pack(ap, dist.data_ptr()))
+    arr = (BatchRangeUpdate * count).from_buffer_copy(b"".join(rows))
+    masks = np.zeros((count, 4), np.uint64)
+    _check(lib().pdm_batch_tf_update_ranges(arr, count, _np_ptr(masks), _stream(stream)),
+           "pdm_batch_tf_update_ranges")
+    del keep
+    return masks
 
 
 # ------------------------------------------------------------- batched build

@@ -354,6 +354,58 @@ pdm_status pdm_batch_tf_update(const pdm_batch_update* h_items, int32_t count,
     return from_hip(pdm::launch_batch_combine(a, stream));
 }
 
+pdm_status pdm_batch_tf_update_ranges(const pdm_batch_range_update* h_items, int32_t count,
+                                      uint64_t* h_active, hipStream_t stream) {
+    if (h_items == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
+    static_assert(PDM_BATCH_MAX <= PDM_BATCH_MAX_ITEMS, "batch descriptors exceed kernel arguments");
+    static_assert(PDM_MAX_PARTITIONS <= PDM_BATCH_MAX_MAPS, "one cover must fit one launch");
+    // every request validated and its cover found before anything is launched
+    uint16_t maps[PDM_BATCH_MAX][PDM_MAX_PARTITIONS];
+    int32_t cnt[PDM_BATCH_MAX];
+    int64_t G[PDM_BATCH_MAX];
+    for (int32_t k = 0; k < count; ++k) {
+        const pdm_batch_range_update& it = h_items[k];
+        pdm_grid g;
+        pdm_status st = check_volume(it.v, &g);
+        if (st != PDM_OK) return st;
+        if (it.d_pdms == nullptr || it.d_dist == nullptr || it.h_alpha == nullptr || it.max_level < 0)
+            return PDM_E_INVAL;
+        st = check_bounds(it.h_bounds, it.n, it.v->levels);
+        if (st != PDM_OK) return st;
+        const int32_t K = range_levels(it.n, it.max_level);
+        if (K > 0 && it.d_table == nullptr) return PDM_E_INVAL;
+        uint64_t mask[4];
+        active_mask(it.h_bounds, it.n, it.h_alpha, mask);
+        if (h_active != nullptr)
+            for (int w = 0; w < 4; ++w) h_active[4 * k + w] = mask[w];
+        int32_t idx[PDM_MAX_PARTITIONS];
+        cnt[k] = cover(it.n, K, mask, idx);
+        for (int32_t j = 0; j < cnt[k]; ++j) maps[k][j] = (uint16_t)idx[j];
+        G[k] = g.count;
+    }
+    // as few launches as the kernel-argument room for map indices allows
+    pdm::BatchMapsArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int32_t k = 0; k < count; ++k) {
+        if (a.nidx + cnt[k] > PDM_BATCH_MAX_MAPS) {
+            const hipError_t e = pdm::launch_batch_maps(a, stream);
+            if (e != hipSuccess) return PDM_E_DEVICE;
+            memset(&a, 0, sizeof(a));
+        }
+        const pdm_batch_range_update& it = h_items[k];
+        pdm::MapsItem& m = a.it[a.count++];
+        m.pdms = it.d_pdms;
+        m.table = it.d_table;
+        m.out = it.d_dist;
+        m.G = G[k];
+        m.map_first = a.nidx;
+        m.map_count = cnt[k];
+        m.n = it.n;
+        for (int32_t j = 0; j < cnt[k]; ++j) a.idx[a.nidx++] = maps[k][j];
+    }
+    return from_hip(pdm::launch_batch_maps(a, stream));
+}
+
 size_t pdm_batch_workspace_bytes(int32_t count) {
     if (count < 1 || count > PDM_BATCH_MAX) return 0;
     return sizeof(pdm::BatchSync) + (size_t)count * sizeof(pdm::BatchVol);

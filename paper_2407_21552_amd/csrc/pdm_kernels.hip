@@ -23,6 +23,7 @@
 //                   range-table maps covering them), 16 bytes per lane.
 //   k_range_level   one level of the range table: min of two maps.
 //   k_batch_combine the TF updates of up to 48 volumes in one launch.
+//   k_batch_combine_maps  the same through range tables (a map list each).
 //   k_batch_rows, k_batch_scan, k_batch_single
 //                   batched build of up to 48 volumes: grouped launches per
 //                   phase, or one cooperative launch with grid barriers.
@@ -1279,6 +1280,61 @@ __global__ void __launch_bounds__(256) k_batch_combine(BatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_batch_combine_maps: the updates of many requests through range tables in
+// one launch.  Each request lists the maps of its cover (PDMs or table maps
+// of its own volume); work-groups find their request by binary search as in
+// k_batch_combine, and a lane min-combines one 16-byte chunk of the listed
+// maps, four at a time (an empty list writes 255); requests of fewer than 16
+// bricks take a byte path.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_batch_combine_maps(BatchMapsArgs a) {
+    int lo = 0, hi = a.count - 1;  // last request with first_block <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)blockIdx.x >= a.it[mid].first_block) lo = mid;
+        else hi = mid - 1;
+    }
+    const MapsItem& it = a.it[lo];
+    const PDM_GLB uint8_t* pdms = glb(it.pdms);
+    const PDM_GLB uint8_t* table = glb(it.table);
+    PDM_GLB uint8_t* out = glb(it.out);
+    const int64_t G = it.G;
+    const int n = it.n, cnt = it.map_count;
+    const uint16_t* ix = a.idx + it.map_first;
+    const int64_t t = ((int64_t)blockIdx.x - it.first_block) * blockDim.x + threadIdx.x;
+    auto map = [&](int j) -> MapPtr {
+        const int q = ix[j];
+        return q < n ? pdms + (int64_t)q * G : table + (int64_t)(q - n) * G;
+    };
+    if (G >= 16) {
+        if (t >= (G + 15) / 16) return;
+        const int64_t off = chunk_off(t, G);
+        ChunkMin acc;
+        int j = 0;
+        for (; j + 4 <= cnt; j += 4) {
+            const MapPtr m[4] = {map(j), map(j + 1), map(j + 2), map(j + 3)};
+            acc.add(m, off);
+        }
+        if (cnt - j == 3) {
+            const MapPtr m[3] = {map(j), map(j + 1), map(j + 2)};
+            acc.add(m, off);
+        } else if (cnt - j == 2) {
+            const MapPtr m[2] = {map(j), map(j + 1)};
+            acc.add(m, off);
+        } else if (cnt - j == 1) {
+            const MapPtr m[1] = {map(j)};
+            acc.add(m, off);
+        }
+        acc.store(out, off);
+    } else {
+        if (t >= G) return;
+        uint32_t v = 255u;
+        for (int j = 0; j < cnt; ++j) v = umin(v, (uint32_t)map(j)[t]);
+        out[t] = (uint8_t)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched build: the one-time initialisation of many volumes in three
 // grouped launches, each covering every volume of the batch:
 //   rows  item (volume, z slice, group of brick rows): brick [min,max] of the
@@ -1713,6 +1769,18 @@ hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
     }
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     k_batch_combine<<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_maps(BatchMapsArgs& a, hipStream_t s) {
+    int64_t blocks = 0;
+    for (int k = 0; k < a.count; ++k) {
+        const int64_t G = a.it[k].G;
+        a.it[k].first_block = blocks;
+        blocks += G >= 16 ? ((G + 15) / 16 + 255) / 256 : 1;
+    }
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    k_batch_combine_maps<<<(unsigned)blocks, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

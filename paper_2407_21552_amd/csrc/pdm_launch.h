@@ -8,6 +8,7 @@
 #define PDM_ALPHA_WORDS 512      // non-zero opacity bitmap: levels <= 16384
 #define PDM_EXACT_MAX_LEVELS 16384  // intensity -> partition table of the EXACT build
 #define PDM_BATCH_MAX_ITEMS 48     // volumes per batched TF update (kernel-argument space)
+#define PDM_BATCH_MAX_MAPS 640     // map indices per batched range-table launch (kernel-argument space)
 
 
 namespace pdm {
@@ -47,6 +48,29 @@ struct BatchArgs {
     int32_t pad;
     BatchItem it[PDM_BATCH_MAX_ITEMS];
 };
+
+// One request of a batched update through range tables (56 bytes): the maps
+// of its cover are idx[map_first .. map_first + map_count), index i < n
+// naming PDM i and i >= n table map i - n.
+struct MapsItem {
+    const uint8_t* pdms;
+    const uint8_t* table;
+    uint8_t* out;
+    int64_t G;
+    int64_t first_block;  // first work-group of this request (set by the launcher)
+    int32_t map_first;
+    int32_t map_count;
+    int32_t n;
+    int32_t pad;
+};
+
+struct BatchMapsArgs {
+    int32_t count;
+    int32_t nidx;
+    MapsItem it[PDM_BATCH_MAX_ITEMS];
+    uint16_t idx[PDM_BATCH_MAX_MAPS];
+};
+static_assert(sizeof(BatchMapsArgs) <= 4000, "kernel arguments of the batched range-table update");
 
 // Persistent batched build: one descriptor per volume in device memory.
 struct BatchVol {
@@ -117,6 +141,8 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
 hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s);
+// One launch for the a.count requests of `a` (sets first_block).
+hipError_t launch_batch_maps(BatchMapsArgs& a, hipStream_t s);
 // Uploads `count` descriptors into d_vols and zeroes d_sync, then runs the
 // build over totals[ph] items per phase: three grouped launches, or with
 // `single` one cooperative launch with grid barriers between the phases; a

@@ -265,8 +265,8 @@ class GpuExecutor(Executor):
     """Runs the server on the GPU through the C ABI.  Admission uploads the
     voxels and builds bricks and PDMs (and, with `range_level`, the range
     table) on `admit_stream`; updates run on `update_stream`, one batched
-    launch per tick (with `range_level`: one update through the table per
-    request).  Each request gets an output map from a per-volume pool of
+    launch per tick (with `range_level`: the batched update through the
+    tables).  Each request gets an output map from a per-volume pool of
     `outputs_per_volume` buffers, used in turn: a result stays valid until
     that many later requests of the same volume have been launched, and one
     launch holds at most that many requests of a volume."""
@@ -280,7 +280,7 @@ class GpuExecutor(Executor):
         self.outputs = int(outputs_per_volume)
         self.keep_volume = keep_volume
         # with a range level, admission also builds each volume's range table
-        # and every request is one update through it (fewer maps read than
+        # and a tick's batch updates through the tables (fewer maps read than
         # the batched update of the active PDMs)
         self.range_level = range_level
 
@@ -347,8 +347,7 @@ class GpuExecutor(Executor):
             req.result = out
             entries.append((h.vol.prepared, alpha, out))
         if self.range_level:
-            for pv, alpha, out in entries:
-                pdm.tf_update_ranges_prepared(pv, alpha, out, self.update_stream)
+            pdm.batch_tf_update_ranges_prepared(entries, self.update_stream)
         else:
             pdm.batch_tf_update_prepared(entries, self.update_stream)
         ev = torch.cuda.Event()

@@ -299,3 +299,37 @@ def test_range_calls_validate(lib):
     assert lib.pdm_range_cover(8, 3, None, ctypes.c_void_p(out.ctypes.data), r(cnt)) == L.PDM_E_INVAL
     assert lib.pdm_range_cover(0, 3, ctypes.c_void_p(m.ctypes.data), ctypes.c_void_p(out.ctypes.data),
                                r(cnt)) == L.PDM_E_INVAL
+
+
+def test_batch_range_update_validates_before_launch(lib):
+    """Every request of a batched range-table update is checked before any
+    launch: a bad request anywhere in the batch fails the whole call with no
+    device work (the fake pointers are never dereferenced)."""
+    d = desc()
+    bnd, pb = _b(W.uniform_bounds(256, 8))
+    alpha = np.ones(256, np.float32)
+    pa = ctypes.c_void_p(alpha.ctypes.data)
+
+    def item(**kw):
+        it = L.BatchRangeUpdate()
+        it.v = ctypes.pointer(d)
+        it.d_pdms, it.d_table, it.h_bounds = FAKE, FAKE, pb
+        it.n, it.max_level, it.h_alpha, it.d_dist = 8, 3, pa, FAKE
+        for k, v in kw.items():
+            setattr(it, k, v)
+        return it
+
+    def call(items, count=None):
+        arr = (L.BatchRangeUpdate * max(1, len(items)))(*items)
+        return lib.pdm_batch_tf_update_ranges(arr, len(items) if count is None else count, NULL, NULL)
+
+    assert lib.pdm_batch_tf_update_ranges(None, 1, NULL, NULL) == L.PDM_E_INVAL
+    assert call([item()], count=0) == L.PDM_E_INVAL
+    assert call([item()] * 49) == L.PDM_E_INVAL
+    bad, pbad = _b([0, 100, 100, 256])
+    for broken in (dict(d_pdms=None), dict(d_dist=None), dict(h_alpha=None), dict(max_level=-1),
+                   dict(d_table=None), dict(h_bounds=pbad, n=3), dict(n=0)):
+        assert call([item(), item(**broken)]) == L.PDM_E_INVAL, broken
+    # no table is needed when the level count is 0 (validation passes; the
+    # call would then launch, so it is not made here)
+    assert L.range_table_maps(8, 0) == 0

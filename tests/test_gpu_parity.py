@@ -512,6 +512,77 @@ def test_combine_wide_ragged_unaligned(pdm, orc):
         assert int(obuf[:9].min()) == 5 and int(obuf[9 + G:].max()) == 5
 
 
+def test_batch_range_update(pdm, orc):
+    """Updates through range tables of many requests in one call: volumes of
+    sizes around the 16-byte chunk (and below it), u8 and u16, different n
+    and max_level, PDMs, tables and outputs at odd byte offsets, an empty S;
+    then a batch whose covers exceed one launch's map list (256 partitions
+    with every other one active: covers of 128 maps, six requests), which the
+    call splits.  Every D' and S mask against the oracle and the single
+    call."""
+    import torch
+    rng = np.random.default_rng(77)
+    cases = [(shape, np.uint8, 256, 12, 3) for shape in COMBINE_SHAPES] + \
+            [((20, 24, 64), np.uint16, 4096, 32, 4), ((30, 30, 30), np.uint8, 256, 64, 0)]
+    vols, items, wants = [], [], []
+    for k, (shape, dtype, L, n, K) in enumerate(cases):
+        vol = blocky(shape, dtype, L, seed=500 + k, keep=0.4, cell=1)
+        bounds = W.uniform_bounds(L, n)
+        v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=dtype)
+        v.build()
+        G = v.G
+        pd_stack = orc.pdms(vol, bounds, L)
+        _, pdms = _at_offset(v.pdms, 1 + k)
+        maps = pdm.range_table_maps(n, K)
+        table = None
+        if maps:
+            tbuf = torch.empty(maps * G + 8, dtype=torch.uint8, device="cuda")
+            table = tbuf[3:3 + maps * G]
+            pdm.build_range_table(v.desc, pdms, n, K, table)
+        alpha = np.zeros(L, np.float32) if k == 2 else W.trapezoid_tf(L, int(rng.integers(1, 5)), rng)
+        _, out = _at_offset(torch.zeros(G, dtype=torch.uint8, device="cuda"), 2 + k)
+        vols.append((v, pdms, table, n, K, out))
+        items.append((v.desc, pdms, table, bounds, K, alpha, out))
+        wants.append(orc.tf_update(pd_stack, bounds, alpha, L))
+    say(f"[case] batched range-table update, {len(items)} requests")
+    masks = pdm.batch_tf_update_ranges(items)
+    torch.cuda.synchronize()
+    for k, ((v, pdms, table, n, K, out), (want, wm), it) in enumerate(zip(vols, wants, items)):
+        np.testing.assert_array_equal(masks[k], wm, err_msg=f"mask {k}")
+        np.testing.assert_array_equal(pdm.from_device(out).reshape(want.shape), want, err_msg=f"D' {k}")
+        single = torch.empty(v.G, dtype=torch.uint8, device="cuda")
+        pdm.tf_update_ranges(v.desc, pdms, table, it[3], K, it[5], single)
+        torch.cuda.synchronize()
+        assert torch.equal(single, out), f"single call {k}"
+    # covers longer than one launch's map list: the call splits the batch
+    shape, L, n, K = (37, 29, 45), 256, 256, 4
+    vol = blocky(shape, np.uint8, L, seed=600, keep=0.6, cell=1)
+    bounds = W.uniform_bounds(L, n)
+    v = pdm.Volume(pdm.to_device(vol), L, bounds)
+    v.build()
+    pd_stack = orc.pdms(vol, bounds, L)
+    table = torch.empty(pdm.range_table_maps(n, K) * v.G, dtype=torch.uint8, device="cuda")
+    pdm.build_range_table(v.desc, v.pdms, n, K, table)
+    items, wants = [], []
+    for j in range(6):
+        alpha = np.zeros(L, np.float32)
+        alpha[j % 2::2] = 0.5                     # every other partition: 128 runs of one
+        if j == 5:
+            alpha[100:180] = 1.0                  # one long run among them
+        out = torch.empty(v.G, dtype=torch.uint8, device="cuda")
+        items.append((v.desc, v.pdms, table, bounds, K, alpha, out))
+        wants.append(orc.tf_update(pd_stack, bounds, alpha, L))
+    covers = [len(pdm.range_cover(n, K, w[1])) for w in wants]
+    assert sum(covers) > 640 and max(covers) == 128
+    say(f"[case] batched range-table update over two launches, covers {covers}")
+    masks = pdm.batch_tf_update_ranges(items)
+    torch.cuda.synchronize()
+    for k, (it, (want, wm)) in enumerate(zip(items, wants)):
+        np.testing.assert_array_equal(masks[k], wm)
+        np.testing.assert_array_equal(pdm.from_device(it[6]).reshape(want.shape), want,
+                                      err_msg=f"split batch D' {k}")
+
+
 # ------------------------------------------------------ batched build
 @pytest.mark.parametrize("config", [None, dict(rows_per_item=1, lines_mult=4, largest_first=1),
                                     dict(rows_per_item=7, lines_mult=1),
