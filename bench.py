@@ -19,7 +19,7 @@ oracle timed on a slab of the same volume (see `cpu_baseline()`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
                        [--no-cpu-baseline] [--calib-copy-mib M]
-                       [--workload tube_tree|batched|served|sweep]
+                       [--workload tube_tree|batched|served|sweep|configs]
 
 --workload served: a Poisson stream of TF changes (2k/s) over 24 resident
 volumes (22 of the batched recipe and two 1024x1024x795 tube trees) served
@@ -31,6 +31,13 @@ servers, where batches form: achieved updates/s, mean batch, p50/p99.
 --workload sweep: partition counts 16..256, uniform and with a partition of
 its own for rho_min, on the CT-like u16 volume, the tube tree and an
 832x832x494 stag-beetle-shaped u8 volume (see run_sweep).
+
+--workload configs: every configuration (64^3 u8, 512x512x460 u16, the
+1024x1024x795 tube tree), every TF of its sequence: TF update and full
+recompute warm (back to back) and cold (L2 and MALL flushed by a 1 GiB write
+before each timed call), GB/s against 8 TB/s and against a device copy
+measured in the same run, the build split by phase, |S| per TF, and the
+oracle on all host threads and on one.
 
 --workload batched: 48 volumes of uneven sizes (96-640 per axis, half u8 and
 half 12-bit u16, 16/32/64 partitions).  Times the batched build (grouped or
@@ -193,8 +200,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="tube_tree",
-                    choices=("tube_tree", "batched", "served", "sweep"))
+                    choices=("tube_tree", "batched", "served", "sweep", "configs"))
     ap.add_argument("--sweep-tfs", type=int, default=40)
+    ap.add_argument("--config-tfs", type=int, default=200,
+                    help="TFs per configuration for --workload configs (c1 has one)")
     ap.add_argument("--range-level", type=int, default=8,
                     help="top level of the range table (the TF updates through it are reported "
                          "beside the plain update)")
@@ -224,6 +233,9 @@ def main():
         return
     if args.workload == "sweep":
         run_sweep(args)
+        return
+    if args.workload == "configs":
+        run_configs(args)
         return
     cfg = W.config_info("c3")
     L, n = cfg["levels"], cfg["n"]
@@ -516,6 +528,242 @@ def run_batched(args):
                       "bytes": upd_bytes,
                       "host_active_set_us": round(host_set_us, 2),
                       "identical_to_loop": same_update},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def host_info() -> dict:
+    """CPU model and thread counts of the machine that runs the oracle."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def oracle_rates(vol, bounds, alphas, levels, max_tfs, budget_s, one_thread_tfs, one_thread_budget_s):
+    """The CPU oracle's throughput (bytes/s) on `vol`: the build with all
+    host threads, then the TF update and the full recompute with all threads
+    and with one (at most the given TF counts, about the given seconds per
+    phase).  The PDMs built once serve both thread counts."""
+    import oracle
+    all_threads = oracle.threads()
+    n = len(bounds) - 1
+    s, V = vol.dtype.itemsize, vol.size
+    t0 = time.perf_counter()
+    bmin, bmax = oracle.bricks(vol)
+    G = bmin.size
+    pd = oracle.pdms(vol, bounds, levels, brick_minmax=(bmin, bmax))
+    t1 = time.perf_counter()
+    out = {"build_Bps": (V * s + 4 * G * s + n * G) / (t1 - t0), "threads": all_threads}
+
+    def phases(max_k, budget):
+        upd_bytes, k, t2 = 0, 0, time.perf_counter()
+        for a in alphas[:max_k]:
+            _, m = oracle.tf_update(pd, bounds, a, levels)
+            upd_bytes += (len(oracle.active_list(m, n)) + 1) * G
+            k += 1
+            if time.perf_counter() - t2 > budget:
+                break
+        t3 = time.perf_counter()
+        r = {"tf_update_Bps": upd_bytes / (t3 - t2), "tf_update_tfs": k}
+        k = 0
+        for a in alphas[:max_k]:
+            oracle.full_recompute(vol, a, levels)
+            k += 1
+            if time.perf_counter() - t3 > budget:
+                break
+        r["full_recompute_Bps"] = k * (V * s + G) / (time.perf_counter() - t3)
+        r["full_recompute_tfs"] = k
+        return r
+
+    out["all_threads"] = phases(max_tfs, budget_s)
+    oracle.set_threads(1)
+    try:
+        out["one_thread"] = phases(one_thread_tfs, one_thread_budget_s)
+    finally:
+        oracle.set_threads(all_threads)
+    return out
+
+
+def run_configs(args):
+    """Per configuration (c1 64^3 u8, c2 512x512x460 u16, c3 1024x1024x795 u8),
+    every TF of its sequence: the TF update and the full recompute timed per
+    call, warm (the previous call's data left in the caches; a spin kernel
+    keeps the device busy across the start event) and cold (a 1 GiB scratch
+    write before every timed call, outside the timing, so that neither L2 nor
+    the 256 MB MALL holds anything of the call's inputs); GB/s as summed bytes over
+    summed time; roofline fractions against 8 TB/s and against a device copy
+    measured in the same process; the build split into bricks, POM + x pass
+    and y/z passes (median of 5); |S| per TF; the CPU oracle on all host
+    threads and on one (c3 on its first 256 z-slices, rates applied to the
+    full volume)."""
+    import torch
+    import paper_2407_21552_amd as pdm
+    import workloads as W
+
+    stream = torch.cuda.current_stream()
+    scratch = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    # copy ceiling: 1 GiB device-to-device, best of 5 (2 GiB moved)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(3)
+    best = 1e9
+    for _ in range(6):
+        a = ev()
+        scratch.copy_(src)
+        b = ev()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    copy_gbps = 2 * (1 << 30) / (best * 1e-3) / 1e9
+    del src
+    torch.cuda.empty_cache()
+    log(f"device copy ceiling {copy_gbps:.0f} GB/s")
+
+    def stats(ms, bytes_each, small):
+        d = {"p50_ms": round(pct(ms, 50), 4), "p90_ms": round(pct(ms, 90), 4),
+             "mean_ms": round(float(np.mean(ms)), 4)}
+        if small:
+            d["p50_us"] = round(1e3 * pct(ms, 50), 2)
+            d["GBps"] = "n/m"
+        else:
+            gbps = sum(bytes_each) / (sum(ms) * 1e-3) / 1e9
+            d["GBps"] = round(gbps, 1)
+            d["frac_hbm_peak"] = round(gbps / HBM_PEAK_GBPS, 4)
+            d["frac_copy_ceiling"] = round(gbps / copy_gbps, 4)
+        return d
+
+    results = []
+    for name in ("c1", "c2", "c3"):
+        c = W.config_info(name)
+        L, n = c["levels"], c["n"]
+        log(f"{name}: generating {c['shape']} ...")
+        vol = W.make_volume(name)
+        bounds = W.uniform_bounds(L, n)
+        alphas = W.make_tfs(name, None if name == "c1" else args.config_tfs)
+        T = len(alphas)
+        t_vol = pdm.to_device(vol)
+        v = pdm.Volume(t_vol, L, bounds, voxel_dtype=vol.dtype)
+        desc, G, V, s = v.desc, v.G, vol.size, vol.dtype.itemsize
+        small = name == "c1"
+        d_full = torch.empty_like(v.dist)
+        sizes = [len(pdm.mask_to_list(pdm.active_set(bounds, a, L), n)) for a in alphas]
+        upd_b = [(k + 1) * G for k in sizes]
+        full_b = [V * s + G] * T
+        # build, median of 5
+        bt = []
+        for _ in range(6):
+            e = [ev()]
+            pdm.build_bricks(desc, t_vol, v.bmin, v.bmax, None, stream)
+            e.append(ev())
+            pdm.pom_distance_x(desc, v.bmin, v.bmax, bounds, v.pdms, stream)
+            e.append(ev())
+            pdm.distance_yz(desc, v.pdms, n, stream)
+            e.append(ev())
+            bt.append(e)
+        torch.cuda.synchronize()
+        bt = bt[1:]
+        build = {k: round(float(np.median([e[i].elapsed_time(e[i + 1]) for e in bt])), 4)
+                 for i, k in enumerate(("bricks_ms", "pom_x_ms", "distance_yz_ms"))}
+        build["total_ms"] = round(sum(build.values()), 4)
+
+        def busy(cold, k):
+            # the device must be busy when the start event is recorded, or the
+            # event fires while the host still prepares the call and the host
+            # time is counted: a 1 GiB write (cold) or a spin that touches no
+            # memory (warm)
+            if cold:
+                scratch.fill_(k & 255)
+            else:
+                torch.cuda._sleep(100_000)
+
+        def timed(cold, fn):
+            out = []
+            for k, a in enumerate(alphas):
+                busy(cold, k)
+                e0 = ev()
+                fn(a)
+                e1 = ev()
+                out.append((e0, e1))
+            torch.cuda.synchronize()
+            return [x.elapsed_time(y) for x, y in out]
+
+        def full_phases(cold):
+            out = []
+            for k, a in enumerate(alphas):
+                busy(cold, k)
+                e0 = ev()
+                pdm.plain_distance_x(desc, t_vol, a, d_full, stream)
+                e1 = ev()
+                pdm.distance_yz(desc, d_full, 1, stream)
+                e2 = ev()
+                out.append((e0, e1, e2))
+            torch.cuda.synchronize()
+            return ([x.elapsed_time(y) for x, y, _ in out], [y.elapsed_time(z) for _, y, z in out])
+
+        upd = lambda a: pdm.tf_update(desc, v.pdms, bounds, a, v.dist, stream)
+        timed(False, upd)  # warm-up
+        rec = {}
+        for mode in ("warm", "cold"):
+            log(f"{name}: {T} TFs, {mode} ...")
+            u = timed(mode == "cold", upd)
+            ox, yz = full_phases(mode == "cold")
+            fm = [a + b for a, b in zip(ox, yz)]
+            rec[mode] = {"tf_update": stats(u, upd_b, small),
+                         "full_recompute": {**stats(fm, full_b, small),
+                                            "occupancy_x_mean_ms": round(float(np.mean(ox)), 4),
+                                            "distance_yz_mean_ms": round(float(np.mean(yz)), 4)},
+                         "speedup_p50": round(pct(fm, 50) / pct(u, 50), 2)}
+        entry = {"config": name, "shape_zyx": list(vol.shape), "dtype": str(vol.dtype), "levels": L,
+                 "partitions": n, "G": G, "seeds": {"volume": c["seed"], "tf_base": c["tf_seed"]},
+                 "tfs": T, "active_partitions": {"mean": round(float(np.mean(sizes)), 2),
+                                                 "min": int(min(sizes)), "max": int(max(sizes)),
+                                                 "per_tf": sizes},
+                 "build": build, **rec}
+        if not args.no_cpu_baseline:
+            host = vol if name != "c3" else np.ascontiguousarray(vol[:256])
+            scale = vol.size / host.size
+            log(f"{name}: CPU oracle, all threads and one ...")
+            r = oracle_rates(host, bounds, alphas, L, T, 15.0, 20, 6.0)
+            cpu = {"build_ms": round(1e3 * (V * s + 4 * G * s + n * G) / r["build_Bps"], 1),
+                   "build_threads": r["threads"]}
+            for label in ("all_threads", "one_thread"):
+                q = r[label]
+                cpu[label] = {"threads": r["threads"] if label == "all_threads" else 1,
+                              "tf_update_ms_per_tf": round(1e3 * float(np.mean(upd_b)) / q["tf_update_Bps"], 3),
+                              "full_recompute_ms_per_tf": round(1e3 * (V * s + G) / q["full_recompute_Bps"], 3),
+                              "tfs_timed": [q["tf_update_tfs"], q["full_recompute_tfs"]]}
+            entry["cpu_oracle"] = {**cpu, "sample": "full volume" if scale == 1 else
+                                   f"first 256 z-slices, rates applied to the full volume ({scale:.2f}x)"}
+        results.append(entry)
+        del v, t_vol, d_full, vol
+        torch.cuda.empty_cache()
+    c3 = results[-1]["cold"]["tf_update"]
+    out = {
+        "metric": "TF update and full recompute per configuration (c1, c2, c3), warm and cold, "
+                  "GB/s and roofline fractions",
+        "value": c3["GBps"],
+        "unit": "GB/s (c3 TF update, cold)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u8",
+        "data": "synthetic (seeded configurations c1-c3)",
+        "config": {"workload": "c1 64^3 u8 n=8; c2 512x512x460 u16 (12-bit) n=32; "
+                               "c3 1024x1024x795 u8 n=64; bricks 4^3", "tfs": args.config_tfs},
+        "copy_ceiling_GBps": round(copy_gbps, 1),
+        "copy_ceiling": "1 GiB device-to-device copy (torch copy_, best of 5), 2 GiB moved",
+        "host": host_info(),
+        "configs": results,
     }
     print(json.dumps(out), flush=True)
 
