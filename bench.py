@@ -187,6 +187,7 @@ def cpu_baseline(vol, bounds, alphas, levels, step_bytes_fn, slab_z=256, tfs=20)
         "full_recompute_ms_per_tf_full_volume": round(
             1e3 * b["full_recompute"] / b["tfs"] / rate_full, 3),
         "build_ms_full_volume": round(1e3 * (b["bricks"] / rate_bricks + b["partitions"] / rate_parts), 1),
+        "host": host_info(),
     }
 
 
