@@ -1764,8 +1764,7 @@ hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s) {
     for (int k = 0; k < a.count; ++k) {
         const int64_t G = a.it[k].G;
         a.it[k].first_block = blocks;
-        a.it[k].blocks = G >= 16 ? ((G + 15) / 16 + 255) / 256 : 1;
-        blocks += a.it[k].blocks;
+        blocks += G >= 16 ? ((G + 15) / 16 + 255) / 256 : 1;
     }
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     k_batch_combine<<<(unsigned)blocks, 256, 0, s>>>(a);

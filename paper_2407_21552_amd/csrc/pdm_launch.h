@@ -39,7 +39,7 @@ struct BatchItem {
     uint8_t* out;
     int64_t G;
     int64_t first_block;  // first work-group of this volume (set by the launcher)
-    int64_t blocks;       // work-groups of this volume (set by the launcher)
+    int64_t pad;
     uint64_t mask[4];     // active partitions
 };
 

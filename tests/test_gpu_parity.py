@@ -369,7 +369,7 @@ def test_batch_tf_update_matches_oracle(pdm, orc):
         v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=dtype)
         v.build()
         alpha = W.trapezoid_tf(L, int(rng.integers(1, 4)), rng) if k != 4 else np.zeros(L, np.float32)
-        # an odd offset into a larger buffer: the byte-wise path
+        # an odd offset into a larger buffer: unaligned chunks
         out = torch.full((v.G + 3,), 7, dtype=torch.uint8, device="cuda")[1:1 + v.G] if k == 2 \
             else torch.empty(v.G, dtype=torch.uint8, device="cuda")
         vols.append((v, out))
