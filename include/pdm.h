@@ -88,7 +88,9 @@ pdm_status pdm_grid_of(const pdm_volume* v, pdm_grid* out);
 
 /* Step 1 of the TF update (Sec. 3.1): S = { p : some intensity i in
  * [h_bounds[p], h_bounds[p+1]-1] has h_alpha[i] != 0 }.  Every intensity of a
- * partition is tested, present in the volume or not; NaN counts as non-zero.
+ * partition is tested, present in the volume or not.  The test is on the bit
+ * pattern, independent of the host's floating-point mode: NaN and subnormal
+ * opacities count as non-zero, -0 as zero.
  * h_bounds: n+1 int32, h_bounds[0] = 0 < ... < h_bounds[n] = levels,
  * n in [1, 256].  h_alpha: `levels` floats.  h_active: 4 words out, bit p of
  * word p/64 set when p is in S.  Host only. */
@@ -116,7 +118,8 @@ pdm_status pdm_build_partitions(const pdm_volume* v, const void* d_bmin, const v
 
 /* TF update (Sec. 3.1, both steps; Eq. 1): S from h_alpha as in
  * pdm_active_set, then d_dist[c] = min over p in S of d_pdms[p*G + c]; 255
- * when S is empty.  Only the PDMs of S are read.  h_active: nullable, 4 words
+ * when S is empty.  Only the PDMs of S are read.  Any G and any pointer
+ * alignment (d_dist must not overlap d_pdms).  h_active: nullable, 4 words
  * out (the S mask). */
 pdm_status pdm_tf_update(const pdm_volume* v, const uint8_t* d_pdms, const int32_t* h_bounds,
                          int32_t n, const float* h_alpha, uint8_t* d_dist, uint64_t* h_active,
@@ -166,7 +169,8 @@ pdm_status pdm_tf_update_ranges(const pdm_volume* v, const uint8_t* d_pdms, cons
 
 /* Plain method (Sec. 2 and Sec. 4.2): from the raw volume, the occupancy of
  * every brick under the TF (occupied when some intensity i in the brick's
- * [min, max] has h_alpha[i] != 0) and its clamped chessboard distance map D.
+ * [min, max] has h_alpha[i] != 0, tested as in pdm_active_set) and its
+ * clamped chessboard distance map D.
  * h_alpha: v->levels floats, levels <= PDM_MAX_PLAIN_LEVELS.  d_dist: G bytes.
  * Equivalent to pdm_plain_distance_x followed by pdm_distance_yz(count = 1).
  * Voxels >= levels are a precondition violation (see pdm_build_bricks). */

@@ -70,6 +70,13 @@ def tfs(levels, count, seed, ramps=(1, 4)):
            for _ in range(count)]
     out.append(np.zeros(levels, np.float32))      # S empty
     out.append(np.ones(levels, np.float32))       # every intensity opaque
+    # -0 is zero; a subnormal and a NaN are non-zero (bit-pattern test on the
+    # host, IEEE comparison in the oracle)
+    special = np.zeros(levels, np.float32)
+    special[:levels // 3] = -0.0
+    special[levels // 2] = np.float32(1e-42)
+    special[-1] = np.nan
+    out.append(special)
     return out
 
 
