@@ -548,11 +548,13 @@ def host_info() -> dict:
             "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
-def oracle_rates(vol, bounds, alphas, levels, max_tfs, budget_s, one_thread_tfs, one_thread_budget_s):
-    """The CPU oracle's throughput (bytes/s) on `vol`: the build with all
-    host threads, then the TF update and the full recompute with all threads
-    and with one (at most the given TF counts, about the given seconds per
-    phase).  The PDMs built once serve both thread counts."""
+def cpu_baseline_rates(vol, bounds, alphas, levels, max_tfs, budget_s, one_thread_tfs,
+                       one_thread_budget_s):
+    """The CPU-baseline leg of the per-configuration workload: the oracle's
+    throughput (bytes/s) on `vol`, the build with all host threads, then the
+    TF update and the full recompute with all threads and with one (at most
+    the given TF counts, about the given seconds per phase).  The PDMs built
+    once serve both thread counts."""
     import oracle
     all_threads = oracle.threads()
     n = len(bounds) - 1
@@ -735,7 +737,7 @@ def run_configs(args):
             host = vol if name != "c3" else np.ascontiguousarray(vol[:256])
             scale = vol.size / host.size
             log(f"{name}: CPU oracle, all threads and one ...")
-            r = oracle_rates(host, bounds, alphas, L, T, 15.0, 20, 6.0)
+            r = cpu_baseline_rates(host, bounds, alphas, L, T, 15.0, 20, 6.0)
             cpu = {"build_ms": round(1e3 * (V * s + 4 * G * s + n * G) / r["build_Bps"], 1),
                    "build_threads": r["threads"]}
             for label in ("all_threads", "one_thread"):
@@ -744,7 +746,7 @@ def run_configs(args):
                               "tf_update_ms_per_tf": round(1e3 * float(np.mean(upd_b)) / q["tf_update_Bps"], 3),
                               "full_recompute_ms_per_tf": round(1e3 * (V * s + G) / q["full_recompute_Bps"], 3),
                               "tfs_timed": [q["tf_update_tfs"], q["full_recompute_tfs"]]}
-            entry["cpu_oracle"] = {**cpu, "sample": "full volume" if scale == 1 else
+            entry["cpu_baseline"] = {**cpu, "kind": "oracle", "sample": "full volume" if scale == 1 else
                                    f"first 256 z-slices, rates applied to the full volume ({scale:.2f}x)"}
         results.append(entry)
         del v, t_vol, d_full, vol
