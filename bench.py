@@ -606,7 +606,8 @@ def run_configs(args):
     measured in the same process; the build split into bricks, POM + x pass
     and y/z passes (median of 5); |S| per TF; the CPU oracle on all host
     threads and on one (c3 on its first 256 z-slices, rates applied to the
-    full volume)."""
+    full volume).  Last, c3's first 100 z-slices: one GPU's share when the
+    volume is split into 8 z-slabs."""
     import torch
     import paper_2407_21552_amd as pdm
     import workloads as W
@@ -647,13 +648,24 @@ def run_configs(args):
         return d
 
     results = []
-    for name in ("c1", "c2", "c3"):
-        c = W.config_info(name)
+    c3_vol = None
+    # c3_slab8: the first 100 z-slices of c3 (25 brick layers), the share of
+    # one GPU when the volume is split into 8 z-slabs (the update and the
+    # slab-local build phases are that GPU's work as they stand; its z pass
+    # would need the other slabs' columns)
+    for name in ("c1", "c2", "c3", "c3_slab8"):
+        c = W.config_info("c3" if name == "c3_slab8" else name)
         L, n = c["levels"], c["n"]
-        log(f"{name}: generating {c['shape']} ...")
-        vol = W.make_volume(name)
+        if name == "c3_slab8":
+            vol = np.ascontiguousarray(c3_vol[:100])
+            c3_vol = None
+        else:
+            log(f"{name}: generating {c['shape']} ...")
+            vol = W.make_volume(name)
+            if name == "c3":
+                c3_vol = vol
         bounds = W.uniform_bounds(L, n)
-        alphas = W.make_tfs(name, None if name == "c1" else args.config_tfs)
+        alphas = W.make_tfs("c3" if name == "c3_slab8" else name, None if name == "c1" else args.config_tfs)
         T = len(alphas)
         t_vol = pdm.to_device(vol)
         v = pdm.Volume(t_vol, L, bounds, voxel_dtype=vol.dtype)
@@ -733,7 +745,11 @@ def run_configs(args):
                                                  "min": int(min(sizes)), "max": int(max(sizes)),
                                                  "per_tf": sizes},
                  "build": build, **rec}
-        if not args.no_cpu_baseline:
+        if name == "c3_slab8":
+            entry["note"] = ("one GPU's share of c3 split into 8 z-slabs; the update and the bricks, "
+                             "POM + x and y phases are that GPU's work, the z pass would need the "
+                             "other slabs' columns (one exchange per volume load)")
+        if not args.no_cpu_baseline and name != "c3_slab8":
             host = vol if name != "c3" else np.ascontiguousarray(vol[:256])
             scale = vol.size / host.size
             log(f"{name}: CPU oracle, all threads and one ...")
@@ -751,7 +767,7 @@ def run_configs(args):
         results.append(entry)
         del v, t_vol, d_full, vol
         torch.cuda.empty_cache()
-    c3 = results[-1]["cold"]["tf_update"]
+    c3 = next(r for r in results if r["config"] == "c3")["cold"]["tf_update"]
     out = {
         "metric": "TF update and full recompute per configuration (c1, c2, c3), warm and cold, "
                   "GB/s and roofline fractions",
@@ -762,7 +778,8 @@ def run_configs(args):
         "dtype": "u8",
         "data": "synthetic (seeded configurations c1-c3)",
         "config": {"workload": "c1 64^3 u8 n=8; c2 512x512x460 u16 (12-bit) n=32; "
-                               "c3 1024x1024x795 u8 n=64; bricks 4^3", "tfs": args.config_tfs},
+                               "c3 1024x1024x795 u8 n=64; c3_slab8 its first 100 z-slices; "
+                               "bricks 4^3", "tfs": args.config_tfs},
         "copy_ceiling_GBps": round(copy_gbps, 1),
         "copy_ceiling": "1 GiB device-to-device copy (torch copy_, best of 5), 2 GiB moved",
         "host": host_info(),
