@@ -1299,11 +1299,16 @@ __global__ void __launch_bounds__(256) k_batch_combine_maps(BatchMapsArgs a) {
     const PDM_GLB uint8_t* table = glb(it.table);
     PDM_GLB uint8_t* out = glb(it.out);
     const int64_t G = it.G;
-    const int n = it.n, cnt = it.map_count;
-    const uint16_t* ix = a.idx + it.map_first;
+    const int n = it.n, cnt = it.map_count, first = it.map_first;
     const int64_t t = ((int64_t)blockIdx.x - it.first_block) * blockDim.x + threadIdx.x;
+    // indices read as 32-bit words at uniform addresses: scalar loads through
+    // the scalar cache (a 16-bit read would be a vector load per lane from
+    // the argument buffer)
+    const uint32_t* ix32 = reinterpret_cast<const uint32_t*>(a.idx);
     auto map = [&](int j) -> MapPtr {
-        const int q = ix[j];
+        const int k = first + j;
+        const uint32_t w = ix32[k >> 1];
+        const int q = (int)((k & 1) ? (w >> 16) : (w & 0xFFFFu));
         return q < n ? pdms + (int64_t)q * G : table + (int64_t)(q - n) * G;
     };
     if (G >= 16) {

@@ -2,6 +2,7 @@
 // kernel launchers.  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime_api.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define PDM_PLAIN_MAX_SEGS 64    // x segments of 256 bricks: Bx <= 16384
@@ -71,6 +72,7 @@ struct BatchMapsArgs {
     uint16_t idx[PDM_BATCH_MAX_MAPS];
 };
 static_assert(sizeof(BatchMapsArgs) <= 4000, "kernel arguments of the batched range-table update");
+static_assert(offsetof(BatchMapsArgs, idx) % 4 == 0, "map indices are read as 32-bit words");
 
 // Persistent batched build: one descriptor per volume in device memory.
 struct BatchVol {

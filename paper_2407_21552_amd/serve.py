@@ -300,6 +300,7 @@ class GpuExecutor(Executor):
         torch = self.torch
         h = GpuExecutor.Handle()
         h.spec = spec
+        h.is_ready = False
         vox = spec.load()
         with torch.cuda.stream(self.admit_stream):
             h.vol = pdm.Volume(pdm.to_device(vox), spec.levels, spec.bounds, voxel_dtype=spec.dtype)
@@ -324,10 +325,13 @@ class GpuExecutor(Executor):
         return h
 
     def ready(self, h) -> bool:
+        if h.is_ready:  # a built volume stays built: no event query per request
+            return True
         ok = h.ready_ev.query()
-        if ok and getattr(h, "drop_volume_after_ready", False):
-            h.vol.volume = None  # voxels are not needed once the PDMs exist
-            h.drop_volume_after_ready = False
+        if ok:
+            h.is_ready = True
+            if h.drop_volume_after_ready:
+                h.vol.volume = None  # voxels are not needed once the PDMs exist
         return ok
 
     def evict(self, h) -> None:
