@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--range-level", type=int, default=8,
                     help="top level of the range table (the TF updates through it are reported "
                          "beside the plain update)")
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-load-rates", default="20000,60000,150000",
                     help="comma-separated request rates of the served load levels")
