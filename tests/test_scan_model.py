@@ -1,0 +1,137 @@
+"""The y/z distance pass's algorithm, modelled step for step in Python and
+checked against the definition (host only; no GPU, no oracle).
+
+The pass computes g(i) = min_j max(|i-j|, f(j)) over one line (the max-min
+recurrence of the separable chessboard distance transform, Sec. 3.1).  The
+kernels run it as a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
+followed by the same pass backwards over F, each in one sweep that keeps
+v = F(i-1), its latest witness W and a table last[w] of the latest position
+holding value w, with the table reads issued one step ahead (the candidates
+for the next step's lookup, resolved once the step's outcome is known).  The
+split variant runs the forward and backward passes at once on two lanes, each
+first over its half of the line and then over the half the other has done,
+with values clamped at min(m, 255) and the line's minimum as the result
+wherever every value is at least that clamp.  These models mirror that logic
+so a change to it can be checked here first."""
+import numpy as np
+import pytest
+
+
+def brute(f):
+    f = np.asarray(f, dtype=np.int64)
+    i = np.arange(len(f))
+    return np.minimum(np.maximum(np.abs(i[:, None] - i[None, :]), f[None, :]).min(axis=1), 255)
+
+
+class Lane:
+    """One lane's scan state (v, W, the pending lookup t and the two reads
+    issued one step ahead with the flags that resolve them)."""
+
+    def __init__(self, rows, v0):
+        self.tbl = [0] * rows
+        self.v, self.W, self.t, self.ra, self.rb, self.ip = v0, 0, 0, 0, 0, 0
+        self.take = self.adv = self.eq = False
+
+    def step(self, i, fi):
+        ran, rbn = self.tbl[fi + 1], self.tbl[self.v + 2]       # reads for the next step
+        advn = (i - self.W) > self.v
+        X = self.v + (1 if advn else 0)
+        taken = fi <= X
+        eqn = fi == X + 1
+        # last[v+1] as of the previous step, from that step's reads
+        t = self.ra if self.take else (self.ip if self.eq else (self.rb if self.adv else self.t))
+        Wb = max(self.W, t) if advn else self.W
+        self.W = i if taken else Wb
+        self.v = fi if taken else X
+        self.take, self.eq, self.adv, self.ip, self.ra, self.rb, self.t = taken, eqn, advn, i, ran, rbn, t
+        self.tbl[fi] = i
+        return self.v
+
+
+def one_sided(col, rows=258):
+    lane = Lane(rows, col[0])
+    out = [col[0]]
+    for i in range(1, len(col)):
+        out.append(lane.step(i, col[i]))
+    return out
+
+
+def two_sided(f):
+    fwd = one_sided([int(x) for x in f])
+    return np.array(one_sided(fwd[::-1])[::-1])
+
+
+def split(f):
+    m = len(f)
+    vmax, h = min(m, 255), m // 2
+    tile = [int(x) for x in f]
+    F, B = Lane(vmax + 3, min(tile[0], vmax)), Lane(vmax + 3, min(tile[m - 1], vmax))
+    raw = [tile[0], tile[m - 1]]
+
+    def run(lane, pos, i, k):
+        r = tile[pos]
+        tile[pos] = lane.step(i, min(r, vmax))
+        if k is not None:
+            raw[k] = min(raw[k], r)
+
+    for i in range(1, h):                      # phase 1: each lane over its half
+        run(F, i, i, 0)
+        run(B, m - 1 - i, i, 1)
+    if m - h > h:
+        run(B, m - 1 - h, h, 1)
+    lmin = min(raw)
+    if m - h > h:
+        run(F, h, h, None)
+    for i in range(m - h, m):                  # phase 2: over the half the other lane did
+        run(F, i, i, None)
+        run(B, m - 1 - i, i, None)
+    if lmin >= vmax:                           # every value >= the clamp: the line's minimum
+        tile = [lmin] * m
+    return np.array(tile)
+
+
+def lines(seed, count, max_m=256):
+    rng = np.random.default_rng(seed)
+    for k in range(count):
+        m = int(rng.integers(1, max_m + 1))
+        kind = k % 6
+        if kind == 0:
+            f = rng.integers(0, 256, m)
+        elif kind == 1:                       # x distances: sparse zeros, the rest capped
+            f = np.where(rng.random(m) < 0.05, 0, 255)
+        elif kind == 2:
+            f = np.minimum(255, rng.integers(0, 40, m) + rng.integers(0, 3) * 100)
+        elif kind == 3:                       # a distance ramp with noise
+            f = np.minimum(255, np.abs(np.arange(m) - rng.integers(0, m)) + rng.integers(0, 5, m))
+        elif kind == 4:                       # every value >= m (the split pass's fix-up)
+            f = rng.integers(m, 256, m) if m < 256 else np.full(m, 255)
+        else:                                 # values around m
+            f = np.minimum(255, rng.integers(max(0, m - 3), m + 3, m))
+        yield f
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_two_sided_scan_matches_definition(seed):
+    for f in lines(seed, 300):
+        np.testing.assert_array_equal(two_sided(f), brute(f), err_msg=str(list(f)))
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_split_scan_matches_definition(seed):
+    for f in lines(seed, 300):
+        np.testing.assert_array_equal(split(f), brute(f), err_msg=str(list(f)))
+
+
+def test_scan_edge_lines():
+    for f in ([0], [255], [7], [0, 255], [255, 0], [3, 3], [255] * 256, [0] * 256,
+              [255] * 255 + [0], [0] + [255] * 255, list(range(256)), list(range(255, -1, -1))):
+        np.testing.assert_array_equal(two_sided(f), brute(f))
+        np.testing.assert_array_equal(split(f), brute(f))
+
+
+def test_longer_lines_with_wide_table():
+    # lines over 256 positions keep positions beyond 255 (16-bit table entries)
+    rng = np.random.default_rng(9)
+    for m in (257, 300):
+        f = np.where(rng.random(m) < 0.02, 0, 255)
+        np.testing.assert_array_equal(two_sided(f), brute(f))
