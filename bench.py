@@ -606,8 +606,10 @@ def run_configs(args):
     measured in the same process; the build split into bricks, POM + x pass
     and y/z passes (median of 5); |S| per TF; the CPU oracle on all host
     threads and on one (c3 on its first 256 z-slices, rates applied to the
-    full volume).  Last, c3's first 100 z-slices: one GPU's share when the
-    volume is split into 8 z-slabs."""
+    full volume).  The same in the EXACT reading (occupancy from the brick's
+    voxels): its build, full recompute and update, and how much larger its
+    distances run than RANGE's.  Last, c3's first 100 z-slices: one GPU's
+    share when the volume is split into 8 z-slabs."""
     import torch
     import paper_2407_21552_amd as pdm
     import workloads as W
@@ -713,12 +715,13 @@ def run_configs(args):
             torch.cuda.synchronize()
             return [x.elapsed_time(y) for x, y in out]
 
-        def full_phases(cold):
+        def full_phases(cold, exact=False):
+            occ_x = pdm.plain_exact_distance_x if exact else pdm.plain_distance_x
             out = []
             for k, a in enumerate(alphas):
                 busy(cold, k)
                 e0 = ev()
-                pdm.plain_distance_x(desc, t_vol, a, d_full, stream)
+                occ_x(desc, t_vol, a, d_full, stream)
                 e1 = ev()
                 pdm.distance_yz(desc, d_full, 1, stream)
                 e2 = ev()
@@ -739,12 +742,66 @@ def run_configs(args):
                                             "occupancy_x_mean_ms": round(float(np.mean(ox)), 4),
                                             "distance_yz_mean_ms": round(float(np.mean(yz)), 4)},
                          "speedup_p50": round(pct(fm, 50) / pct(u, 50), 2)}
+        # EXACT reading (occupancy from the brick's voxels): build, full
+        # recompute warm and cold, and the update over the EXACT PDMs; and how
+        # much larger its distances run than RANGE's (EXACT occupancy is a
+        # subset, so its distances are >= RANGE's)
+        exact = None
+        if name != "c3_slab8":
+            pdms_x = torch.empty_like(v.pdms)
+            d_xu = torch.empty_like(v.dist)
+            bx = []
+            for _ in range(6):
+                e = [ev()]
+                pdm.pom_exact_distance_x(desc, t_vol, bounds, pdms_x, stream)
+                e.append(ev())
+                pdm.distance_yz(desc, pdms_x, n, stream)
+                e.append(ev())
+                bx.append(e)
+            torch.cuda.synchronize()
+            bx = bx[1:]
+            xb = {"pom_exact_x_ms": round(float(np.median([e[0].elapsed_time(e[1]) for e in bx])), 4),
+                  "distance_yz_ms": round(float(np.median([e[1].elapsed_time(e[2]) for e in bx])), 4)}
+            xb["total_ms"] = round(xb["pom_exact_x_ms"] + xb["distance_yz_ms"], 4)
+            xupd = lambda a: pdm.tf_update(desc, pdms_x, bounds, a, d_xu, stream)
+            timed(False, xupd)  # warm-up
+            xrec = {}
+            for mode in ("warm", "cold"):
+                log(f"{name}: EXACT, {T} TFs, {mode} ...")
+                u = timed(mode == "cold", xupd)
+                ox, yz = full_phases(mode == "cold", exact=True)
+                fm = [a + b for a, b in zip(ox, yz)]
+                xrec[mode] = {"tf_update": stats(u, upd_b, small),
+                              "full_recompute": {**stats(fm, full_b, small),
+                                                 "occupancy_x_mean_ms": round(float(np.mean(ox)), 4),
+                                                 "distance_yz_mean_ms": round(float(np.mean(yz)), 4)}}
+            # tightness on three TFs: D' and D in both readings
+            cmp_ = []
+            for a in alphas[:3]:
+                pdm.tf_update(desc, v.pdms, bounds, a, v.dist, stream)
+                pdm.tf_update(desc, pdms_x, bounds, a, d_xu, stream)
+                pdm.full_recompute(desc, t_vol, a, d_full, stream)
+                dxf = torch.empty_like(d_full)
+                pdm.full_recompute_exact(desc, t_vol, a, dxf, stream)
+                torch.cuda.synchronize()
+                r_dp, x_dp = v.dist.float(), d_xu.float()
+                cmp_.append({"dprime_exact_gt_range_frac": float((d_xu > v.dist).float().mean()),
+                             "dprime_mean_range": float(r_dp.mean()),
+                             "dprime_mean_exact": float(x_dp.mean()),
+                             "d_exact_gt_range_frac": float((dxf > d_full).float().mean()),
+                             "exact_dprime_le_exact_d": bool((d_xu <= dxf).all())})
+            exact = {"build": xb, **xrec,
+                     "vs_range": {k: (round(float(np.mean([c[k] for c in cmp_])), 4) if k != "exact_dprime_le_exact_d"
+                                      else all(c[k] for c in cmp_)) for k in cmp_[0]}}
+            del pdms_x, d_xu
         entry = {"config": name, "shape_zyx": list(vol.shape), "dtype": str(vol.dtype), "levels": L,
                  "partitions": n, "G": G, "seeds": {"volume": c["seed"], "tf_base": c["tf_seed"]},
                  "tfs": T, "active_partitions": {"mean": round(float(np.mean(sizes)), 2),
                                                  "min": int(min(sizes)), "max": int(max(sizes)),
                                                  "per_tf": sizes},
                  "build": build, **rec}
+        if exact is not None:
+            entry["exact"] = exact
         if name == "c3_slab8":
             entry["note"] = ("one GPU's share of c3 split into 8 z-slabs; the update and the bricks, "
                              "POM + x and y phases are that GPU's work, the z pass would need the "
