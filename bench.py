@@ -352,9 +352,9 @@ def main():
         return r
 
     total_by_kernel = {
-        "k_plain_x": sum(plx_ms), "k_dist_axis(full recompute)": sum(dyz1_ms),
+        "k_plain_x": sum(plx_ms), "y/z scans, one map (k_dist_axis + k_dist_split)": sum(dyz1_ms),
         "k_combine": sum(upd_ms), "k_bricks": sum(bricks_ms), "k_pom_x": sum(pomx_ms),
-        "k_dist_axis(partitions)": sum(dyz_n_ms)}
+        "y/z scans, all partitions (k_dist_global)": sum(dyz_n_ms)}
 
     out = {
         "metric": "TF-update ms & GB/s (partitioned vs full recompute), 1024³ u8; p50/p99 served",
