@@ -65,7 +65,7 @@ typedef enum {
     PDM_OK = 0,
     PDM_E_INVAL = -1,       /* bad pointer, size, dtype, levels or bounds */
     PDM_E_RANGE = -2,       /* reserved: data-dependent range errors go to d_range_err */
-    PDM_E_UNSUPPORTED = -3, /* valid but not handled by this build (brick != 4, sizes) */
+    PDM_E_UNSUPPORTED = -3, /* valid but not handled by these kernels (brick != 4, sizes) */
     PDM_E_DEVICE = -4       /* a kernel launch failed */
 } pdm_status;
 
@@ -233,7 +233,7 @@ pdm_status pdm_batch_tf_update_ranges(const pdm_batch_range_update* h_items, int
  * d_workspace: device memory of pdm_batch_workspace_bytes(count) bytes,
  * 16-byte aligned, owned by the caller; it receives the barrier state and the
  * volume descriptors and must not be used by another call until the stream
- * has passed this build.  Its first 4 bytes are an error word, zeroed by the
+ * has passed this batched build.  Its first 4 bytes are an error word, zeroed by the
  * call: non-zero once the stream has passed the build means a single-launch
  * barrier wait gave up after its time limit (never expected; the outputs
  * are then incomplete).  The grouped launches leave it zero.

@@ -701,19 +701,20 @@ __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol
 // followed by the same pass backwards over F, which yields g exactly (a
 // candidate j > i reaches i only through the backward pass, j <= i through
 // the forward one).  The one-sided pass runs in one sweep: keep v = F(i-1)
-// and W = the latest j attaining it (max(i-1-j, f(j)) <= v).  Then F(i) is
-// min(f(i), X) with X = v if i-W <= v, else v+1; in the second case the new
-// latest witness is W or the latest j in the window with f(j) = v+1, held in
-// a per-lane table last[w] = latest position with value w.  Table entries
-// start at 0; a real position 0 is never needed because an accepted entry
-// must exceed W >= 0.
+// and a witness W with max(i-1-W, f(W)) <= v.  Then F(i) is min(f(i), X)
+// with X = v if i-W <= v, else v+1.  In the second case the next witness is
+// the latest position holding exactly v+1, looked up in a per-lane table
+// last[w] = latest position with value w.  The exact rule would keep the
+// later of that entry and W; taking the entry alone changes no later
+// decision, because when it is the earlier one, W itself was already too far
+// for v+1 at the next position, so both choices advance again there.  An
+// empty entry (0) behaves the same way.
 //
-// Latency: the lookup last[v+1] of step i+1 depends on v = F(i).  Each step
-// therefore reads, one step ahead, the two entries v can lead to besides
-// last[v+1] itself -- last[f(i)+1] (F(i) = f(i)) and last[v+2] (F(i) = v+1)
-// -- and picks one once F(i) is known; an entry equal to the value written
-// in the same step is replaced by that position.  The table load is thus off
-// the dependency chain between steps.
+// Latency: step i writes last[f(i)] = i and then reads the three entries the
+// next step can need -- last[f(i)+1] (F(i) = f(i)), last[v+1] (F(i) = v) and
+// last[v+2] (F(i) = v+1).  They are issued after the write, so they see it,
+// and the next step picks one by how this step ended.  The table load is
+// thus off the dependency chain between steps.
 //
 // Tables: 258 rows (values 0..257, the last two never written) of kPitch
 // entries, lane-major inside a row; the odd dword pitch (17) spreads lanes
@@ -736,33 +737,34 @@ __device__ __forceinline__ void clear_table(P* tbl) {
 }
 
 // One step of the one-sided pass at position i (i >= 1) with input fi.
-// State: v = F(i-1), W its latest witness, t = last[v+1]; ra/rb are the
-// candidates last[f+1], last[v+2] read in the previous step and resolved in
-// this one by how that step ended (take: F = f; eq: the entry was the one
-// written in that step, at position ip; adv: F = v+1).  The empty asm pins
-// the point where those loads must have returned to after this step's own
-// loads are issued, so the table latency overlaps a step of arithmetic.
+// State: v = F(i-1), W its witness; ra/rc/rb are the entries last[f+1],
+// last[v+1], last[v+2] read in the previous step, resolved by how that step
+// ended (take: F = f; adv: F = v+1; neither: F = v).  Table offsets are
+// 32-bit: v stays below 2^8 (an unsigned min with the 8-bit input), so rows
+// times kPitch plus the lane stays far below 2^24.  The empty
+// asm pins the point where those reads must have returned to after this
+// step's own reads are issued, so the table latency overlaps a step of
+// arithmetic.
 #define PDM_SCAN_STEP(i_, fi_, out_)                                              \
     {                                                                             \
         const int i__ = (i_), fi__ = (fi_);                                       \
-        const int ran__ = (int)tbl[__umul24((unsigned)fi__ + 1u, kPitch) + lane];                   \
-        const int rbn__ = (int)tbl[__umul24((unsigned)v + 2u, kPitch) + lane];                      \
-        const bool advn__ = (i__ - W) > v;                                        \
-        const int X__ = v + (advn__ ? 1 : 0);                                     \
-        const bool taken__ = fi__ <= X__;                                         \
-        const bool eqn__ = fi__ == X__ + 1;                                       \
-        __asm__ volatile("" : "+v"(ra), "+v"(rb));                                \
-        t = take ? ra : (eq ? ip : (adv ? rb : t));                               \
-        const int Wb__ = advn__ ? max(W, t) : W;                                  \
-        W = taken__ ? i__ : Wb__;                                                 \
-        v = taken__ ? fi__ : X__;                                                 \
-        take = taken__;                                                           \
-        eq = eqn__;                                                               \
-        adv = advn__;                                                             \
-        ip = i__;                                                                 \
+        const unsigned af__ = __umul24((unsigned)fi__, (unsigned)kPitch) + (unsigned)lane; \
+        const unsigned av__ = __umul24((unsigned)v, (unsigned)kPitch) + (unsigned)lane;    \
+        tbl[af__] = (P)i__;                                                       \
+        const int ran__ = (int)tbl[af__ + kPitch];                                \
+        const int rcn__ = (int)tbl[av__ + kPitch];                                \
+        const int rbn__ = (int)tbl[av__ + 2 * kPitch];                            \
+        __asm__ volatile("" : "+v"(ra), "+v"(rb), "+v"(rc));                      \
+        const int t__ = take ? ra : (adv ? rb : rc);                              \
+        adv = (i__ - W) > v;                                                      \
+        const int X__ = v + (adv ? 1 : 0);                                        \
+        const int Wn__ = adv ? t__ : W;                                           \
+        take = fi__ <= X__;                                                       \
+        W = take ? i__ : Wn__;                                                    \
+        v = (int)umin((unsigned)fi__, (unsigned)X__);                             \
         ra = ran__;                                                               \
         rb = rbn__;                                                               \
-        tbl[__umul24((unsigned)fi__, kPitch) + lane] = (P)i__;                                       \
+        rc = rcn__;                                                               \
         out_ = v;                                                                 \
     }
 
@@ -775,15 +777,17 @@ __device__ __forceinline__ void one_sided_lds(uint8_t* col, int cs, int m, P* __
     const int lane = threadIdx.x;
     // F(0) = f(0); its table entry (position 0) equals the cleared value
     int v = col[0];
-    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
-    bool take = false, adv = false, eq = false;
+    int W = 0, ra = 0, rb = 0, rc = 0;
+    bool take = false, adv = false;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) f[k] = col[(c + k) * cs];
+        int pc = c;  // the position in a vector register: one add per step
+        __asm__ volatile("" : "+v"(pc));
 #pragma unroll
-        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(pc + k, f[k], f[k]);
 #pragma unroll
         for (int k = 0; k < CH; ++k) col[(c + k) * cs] = (uint8_t)f[k];
     }
@@ -801,15 +805,17 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
                                                  P* __restrict__ tbl) {
     const int lane = threadIdx.x;
     int v = active ? (int)p[0] : 0;
-    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
-    bool take = false, adv = false, eq = false;
+    int W = 0, ra = 0, rb = 0, rc = 0;
+    bool take = false, adv = false;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
 #pragma unroll
         for (int k = 0; k < CH; ++k) f[k] = active ? (int)p[(int64_t)(c + k) * step] : 0;
+        int pc = c;  // the position in a vector register: one add per step
+        __asm__ volatile("" : "+v"(pc));
 #pragma unroll
-        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(pc + k, f[k], f[k]);
         if (active) {
 #pragma unroll
             for (int k = 0; k < CH; ++k) p[(int64_t)(c + k) * step] = (uint8_t)f[k];
@@ -830,8 +836,8 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
 template <int CH>
 __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib, int ie, int vmax,
                                                     bool track, uint8_t* __restrict__ tbl, int& v,
-                                                    int& W, int& t, int& ra, int& rb, int& ip,
-                                                    bool& take, bool& adv, bool& eq, int& raw_min) {
+                                                    int& W, int& ra, int& rb, int& rc, bool& take,
+                                                    bool& adv, int& raw_min) {
     using P = uint8_t;  // table entry type of PDM_SCAN_STEP
     const int lane = threadIdx.x;
     int c = ib;
@@ -841,10 +847,12 @@ __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib
         for (int k = 0; k < CH; ++k) {
             const int r = col[(c + k) * cs];
             if (track) raw_min = min(raw_min, r);
-            f[k] = min(r, vmax);
+            f[k] = (int)umin((unsigned)r, (unsigned)vmax);
         }
+        int pc = c;  // the position in a vector register: one add per step
+        __asm__ volatile("" : "+v"(pc));
 #pragma unroll
-        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(c + k, f[k], f[k]);
+        for (int k = 0; k < CH; ++k) PDM_SCAN_STEP(pc + k, f[k], f[k]);
 #pragma unroll
         for (int k = 0; k < CH; ++k) col[(c + k) * cs] = (uint8_t)f[k];
     }
@@ -852,7 +860,7 @@ __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib
         const int r = col[c * cs];
         if (track) raw_min = min(raw_min, r);
         int out;
-        PDM_SCAN_STEP(c, min(r, vmax), out);
+        PDM_SCAN_STEP(c, (int)umin((unsigned)r, (unsigned)vmax), out);
         col[c * cs] = (uint8_t)out;
     }
 }
@@ -978,22 +986,22 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__
     const int cs = half == 0 ? 32 : -32;
     int raw_min = col[0];
     int v = min(raw_min, vmax);
-    int W = 0, t = 0, ra = 0, rb = 0, ip = 0;
-    bool take = false, adv = false, eq = false;
+    int W = 0, ra = 0, rb = 0, rc = 0;
+    bool take = false, adv = false;
     // phase 1: forward lanes steps [1, h), backward lanes [1, m - h)
-    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, t, ra, rb, ip, take, adv, eq,
+    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, ra, rb, rc, take, adv,
                             raw_min);
     if (m - h > h && half == 1)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, t, ra, rb, ip, take, adv,
-                               eq, raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, ra, rb, rc, take, adv,
+                               raw_min);
     __builtin_amdgcn_wave_barrier();
     const int lmin = min(raw_min, __shfl_xor(raw_min, 32, kScanLanes));
     // phase 2: forward lanes steps [h, m), backward lanes [m - h, m)
     if (m - h > h && half == 0)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, t, ra, rb, ip, take, adv,
-                               eq, raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, ra, rb, rc, take, adv,
+                               raw_min);
     __builtin_amdgcn_wave_barrier();
-    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, t, ra, rb, ip, take, adv, eq,
+    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, ra, rb, rc, take, adv,
                             raw_min);
     // every value of the line >= vmax: the two-sided result is the minimum
     if (lmin >= vmax) {

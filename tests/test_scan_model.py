@@ -5,13 +5,15 @@ The pass computes g(i) = min_j max(|i-j|, f(j)) over one line (the max-min
 recurrence of the separable chessboard distance transform, Sec. 3.1).  The
 kernels run it as a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
 followed by the same pass backwards over F, each in one sweep that keeps
-v = F(i-1), its latest witness W and a table last[w] of the latest position
-holding value w, with the table reads issued one step ahead (the candidates
-for the next step's lookup, resolved once the step's outcome is known).  The
-split variant runs the forward and backward passes at once on two lanes, each
-first over its half of the line and then over the half the other has done,
-with values clamped at min(m, 255) and the line's minimum as the result
-wherever every value is at least that clamp.  These models mirror that logic
+v = F(i-1), a witness W and a table last[w] of the latest position holding
+value w.  Each step writes its own entry first and then reads the three
+entries the next step can need (last[f+1], last[v+1], last[v+2]), resolved
+once the step's outcome is known; on an advance the witness becomes the
+table entry alone, with no max against the old witness.  The split variant
+runs the forward and backward passes at once on two lanes, each first over
+its half of the line and then over the half the other has done, with values
+clamped at min(m, 255) and the line's minimum as the result wherever every
+value is at least that clamp.  These models mirror that logic
 so a change to it can be checked here first."""
 import numpy as np
 import pytest
@@ -24,27 +26,29 @@ def brute(f):
 
 
 class Lane:
-    """One lane's scan state (v, W, the pending lookup t and the two reads
-    issued one step ahead with the flags that resolve them)."""
+    """One lane's scan state (v, W and the three reads issued in the previous
+    step with the flags that resolve them)."""
 
     def __init__(self, rows, v0):
         self.tbl = [0] * rows
-        self.v, self.W, self.t, self.ra, self.rb, self.ip = v0, 0, 0, 0, 0, 0
-        self.take = self.adv = self.eq = False
+        self.v, self.W = v0, 0
+        self.ra = self.rb = self.rc = 0
+        self.take = self.adv = False
 
     def step(self, i, fi):
-        ran, rbn = self.tbl[fi + 1], self.tbl[self.v + 2]       # reads for the next step
-        advn = (i - self.W) > self.v
-        X = self.v + (1 if advn else 0)
-        taken = fi <= X
-        eqn = fi == X + 1
-        # last[v+1] as of the previous step, from that step's reads
-        t = self.ra if self.take else (self.ip if self.eq else (self.rb if self.adv else self.t))
-        Wb = max(self.W, t) if advn else self.W
-        self.W = i if taken else Wb
-        self.v = fi if taken else X
-        self.take, self.eq, self.adv, self.ip, self.ra, self.rb, self.t = taken, eqn, advn, i, ran, rbn, t
+        v = self.v
+        # this step's entry, then the reads for the next step (they see it)
         self.tbl[fi] = i
+        ran, rcn, rbn = self.tbl[fi + 1], self.tbl[v + 1], self.tbl[v + 2]
+        # last[v+1] after the previous step, from that step's reads
+        t = self.ra if self.take else (self.rb if self.adv else self.rc)
+        adv = (i - self.W) > v
+        X = v + (1 if adv else 0)
+        Wn = t if adv else self.W
+        take = fi <= X
+        self.W = i if take else Wn
+        self.v = min(fi, X)
+        self.take, self.adv, self.ra, self.rb, self.rc = take, adv, ran, rbn, rcn
         return self.v
 
 
