@@ -710,11 +710,11 @@ __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol
 // for v+1 at the next position, so both choices advance again there.  An
 // empty entry (0) behaves the same way.
 //
-// Latency: step i writes last[f(i)] = i and then reads the three entries the
-// next step can need -- last[f(i)+1] (F(i) = f(i)), last[v+1] (F(i) = v) and
-// last[v+2] (F(i) = v+1).  They are issued after the write, so they see it,
-// and the next step picks one by how this step ended.  The table load is
-// thus off the dependency chain between steps.
+// Each step writes last[f(i)] = i and then reads last[F(i)+1] for the next
+// step; the read comes after the write, so it sees it.  Reading the next
+// step's candidates ahead (to keep the read off the chain between steps)
+// measured slower: the pass is bound by instructions per step, not by the
+// table's latency.
 //
 // Tables: 258 rows (values 0..257, the last two never written) of kPitch
 // entries, lane-major inside a row; the odd dword pitch (17) spreads lanes
@@ -737,34 +737,19 @@ __device__ __forceinline__ void clear_table(P* tbl) {
 }
 
 // One step of the one-sided pass at position i (i >= 1) with input fi.
-// State: v = F(i-1), W its witness; ra/rc/rb are the entries last[f+1],
-// last[v+1], last[v+2] read in the previous step, resolved by how that step
-// ended (take: F = f; adv: F = v+1; neither: F = v).  Table offsets are
+// State: v = F(i-1), W its witness, t = last[v+1].  Table offsets are
 // 32-bit: v stays below 2^8 (an unsigned min with the 8-bit input), so rows
-// times kPitch plus the lane stays far below 2^24.  The empty
-// asm pins the point where those reads must have returned to after this
-// step's own reads are issued, so the table latency overlaps a step of
-// arithmetic.
+// times kPitch plus the lane stays far below 2^24.
 #define PDM_SCAN_STEP(i_, fi_, out_)                                              \
     {                                                                             \
         const int i__ = (i_), fi__ = (fi_);                                       \
-        const unsigned af__ = __umul24((unsigned)fi__, (unsigned)kPitch) + (unsigned)lane; \
-        const unsigned av__ = __umul24((unsigned)v, (unsigned)kPitch) + (unsigned)lane;    \
-        tbl[af__] = (P)i__;                                                       \
-        const int ran__ = (int)tbl[af__ + kPitch];                                \
-        const int rcn__ = (int)tbl[av__ + kPitch];                                \
-        const int rbn__ = (int)tbl[av__ + 2 * kPitch];                            \
-        __asm__ volatile("" : "+v"(ra), "+v"(rb), "+v"(rc));                      \
-        const int t__ = take ? ra : (adv ? rb : rc);                              \
-        adv = (i__ - W) > v;                                                      \
-        const int X__ = v + (adv ? 1 : 0);                                        \
-        const int Wn__ = adv ? t__ : W;                                           \
-        take = fi__ <= X__;                                                       \
-        W = take ? i__ : Wn__;                                                    \
+        tbl[__umul24((unsigned)fi__, (unsigned)kPitch) + (unsigned)lane] = (P)i__; \
+        const bool adv__ = (i__ - W) > v;                                         \
+        const int X__ = v + (adv__ ? 1 : 0);                                      \
+        const int Wn__ = adv__ ? t : W;                                           \
+        W = fi__ <= X__ ? i__ : Wn__;                                             \
         v = (int)umin((unsigned)fi__, (unsigned)X__);                             \
-        ra = ran__;                                                               \
-        rb = rbn__;                                                               \
-        rc = rcn__;                                                               \
+        t = (int)tbl[__umul24((unsigned)v + 1u, (unsigned)kPitch) + (unsigned)lane]; \
         out_ = v;                                                                 \
     }
 
@@ -777,8 +762,7 @@ __device__ __forceinline__ void one_sided_lds(uint8_t* col, int cs, int m, P* __
     const int lane = threadIdx.x;
     // F(0) = f(0); its table entry (position 0) equals the cleared value
     int v = col[0];
-    int W = 0, ra = 0, rb = 0, rc = 0;
-    bool take = false, adv = false;
+    int W = 0, t = 0;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
@@ -805,8 +789,7 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
                                                  P* __restrict__ tbl) {
     const int lane = threadIdx.x;
     int v = active ? (int)p[0] : 0;
-    int W = 0, ra = 0, rb = 0, rc = 0;
-    bool take = false, adv = false;
+    int W = 0, t = 0;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
@@ -836,8 +819,7 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
 template <int CH>
 __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib, int ie, int vmax,
                                                     bool track, uint8_t* __restrict__ tbl, int& v,
-                                                    int& W, int& ra, int& rb, int& rc, bool& take,
-                                                    bool& adv, int& raw_min) {
+                                                    int& W, int& t, int& raw_min) {
     using P = uint8_t;  // table entry type of PDM_SCAN_STEP
     const int lane = threadIdx.x;
     int c = ib;
@@ -986,23 +968,18 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__
     const int cs = half == 0 ? 32 : -32;
     int raw_min = col[0];
     int v = min(raw_min, vmax);
-    int W = 0, ra = 0, rb = 0, rc = 0;
-    bool take = false, adv = false;
+    int W = 0, t = 0;
     // phase 1: forward lanes steps [1, h), backward lanes [1, m - h)
-    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, ra, rb, rc, take, adv,
-                            raw_min);
+    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, t, raw_min);
     if (m - h > h && half == 1)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, ra, rb, rc, take, adv,
-                               raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, t, raw_min);
     __builtin_amdgcn_wave_barrier();
     const int lmin = min(raw_min, __shfl_xor(raw_min, 32, kScanLanes));
     // phase 2: forward lanes steps [h, m), backward lanes [m - h, m)
     if (m - h > h && half == 0)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, ra, rb, rc, take, adv,
-                               raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, t, raw_min);
     __builtin_amdgcn_wave_barrier();
-    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, ra, rb, rc, take, adv,
-                            raw_min);
+    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, t, raw_min);
     // every value of the line >= vmax: the two-sided result is the minimum
     if (lmin >= vmax) {
         const int n = half == 0 ? m - h : h;  // this lane's phase-2 positions

@@ -6,14 +6,13 @@ recurrence of the separable chessboard distance transform, Sec. 3.1).  The
 kernels run it as a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
 followed by the same pass backwards over F, each in one sweep that keeps
 v = F(i-1), a witness W and a table last[w] of the latest position holding
-value w.  Each step writes its own entry first and then reads the three
-entries the next step can need (last[f+1], last[v+1], last[v+2]), resolved
-once the step's outcome is known; on an advance the witness becomes the
-table entry alone, with no max against the old witness.  The split variant
-runs the forward and backward passes at once on two lanes, each first over
-its half of the line and then over the half the other has done, with values
-clamped at min(m, 255) and the line's minimum as the result wherever every
-value is at least that clamp.  These models mirror that logic
+value w.  Each step writes its own entry first and then reads last[F(i)+1]
+for the next step (so the read sees the write); on an advance the witness
+becomes that table entry alone, with no max against the old witness.  The
+split variant runs the forward and backward passes at once on two lanes, each
+first over its half of the line and then over the half the other has done,
+with values clamped at min(m, 255) and the line's minimum as the result
+wherever every value is at least that clamp.  These models mirror that logic
 so a change to it can be checked here first."""
 import numpy as np
 import pytest
@@ -26,29 +25,21 @@ def brute(f):
 
 
 class Lane:
-    """One lane's scan state (v, W and the three reads issued in the previous
-    step with the flags that resolve them)."""
+    """One lane's scan state: v = F(i-1), the witness W and t = last[v+1]."""
 
     def __init__(self, rows, v0):
         self.tbl = [0] * rows
-        self.v, self.W = v0, 0
-        self.ra = self.rb = self.rc = 0
-        self.take = self.adv = False
+        self.v, self.W, self.t = v0, 0, 0
 
     def step(self, i, fi):
-        v = self.v
-        # this step's entry, then the reads for the next step (they see it)
         self.tbl[fi] = i
-        ran, rcn, rbn = self.tbl[fi + 1], self.tbl[v + 1], self.tbl[v + 2]
-        # last[v+1] after the previous step, from that step's reads
-        t = self.ra if self.take else (self.rb if self.adv else self.rc)
+        v = self.v
         adv = (i - self.W) > v
         X = v + (1 if adv else 0)
-        Wn = t if adv else self.W
-        take = fi <= X
-        self.W = i if take else Wn
+        Wn = self.t if adv else self.W
+        self.W = i if fi <= X else Wn
         self.v = min(fi, X)
-        self.take, self.adv, self.ra, self.rb, self.rc = take, adv, ran, rbn, rcn
+        self.t = self.tbl[self.v + 1]
         return self.v
 
 
