@@ -728,6 +728,17 @@ constexpr int kMaxLine = 256;   // longest line staged in LDS
 // fill the chip's 1024 SIMDs with more than a few waves each, so per-wave
 // latency matters more than occupancy.
 constexpr int64_t kStagedMaxLines = 4 * 1024 * kScanLanes;
+// Steps per chunk of the global-memory scans (values loaded into registers
+// before their steps run).  Measured over all maps of a grid, 32 against 16:
+// 3% faster for 256x256x199 (64 maps: lines of 256 and 199 bricks, over 3M
+// lines per pass) and for 208-brick lines of 208x208x124; 5-10% slower for
+// 128- and 115-brick lines, for 256-brick lines when only 0.4M of them share
+// the pass, and for the batched scans (lines of 24 to 160 bricks).  Lines
+// shorter than a chunk run step by step.
+constexpr int kLongChunk = 32;
+constexpr int kLongChunkLine = 192;
+constexpr int64_t kLongChunkLines = 1 << 20;
+constexpr int kBatchChunk = 16;
 
 template <typename P>
 __device__ __forceinline__ void clear_table(P* tbl) {
@@ -1003,7 +1014,7 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__
 // nine waves share a compute unit: the choice when the passes cover many
 // lines (all partitions at once) and occupancy hides the memory latency.
 // P = uint16_t serves lines longer than 256 bricks (positions beyond 255).
-template <typename P>
+template <typename P, int CH>
 __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict__ maps,
                                                             int64_t lines, int Bx, int inner,
                                                             int64_t plane, int64_t stride, int m,
@@ -1016,11 +1027,11 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_global(uint8_t* __restrict_
     uint8_t* line = maps + (active ? line_offset(l, Bx, inner, plane, G) : 0);
     clear_table<P>(tbl);
     __syncthreads();
-    one_sided_global<P, 16>(line, stride, m, active, tbl);
+    one_sided_global<P, CH>(line, stride, m, active, tbl);
     __syncthreads();
     clear_table<P>(tbl);
     __syncthreads();
-    one_sided_global<P, 16>(line + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
+    one_sided_global<P, CH>(line + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,11 +1448,11 @@ __device__ __forceinline__ void batch_scan_item(const BatchVol* __restrict__ vol
             PDM_GLB uint8_t* q = (PDM_GLB uint8_t*)d.pdms + (active ? base : 0);
             clear_table<uint8_t>(tbl);
             __builtin_amdgcn_wave_barrier();
-            one_sided_global<uint8_t, 16>(q, stride, m, active, tbl);
+            one_sided_global<uint8_t, kBatchChunk>(q, stride, m, active, tbl);
             __builtin_amdgcn_wave_barrier();
             clear_table<uint8_t>(tbl);
             __builtin_amdgcn_wave_barrier();
-            one_sided_global<uint8_t, 16>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
+            one_sided_global<uint8_t, kBatchChunk>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
         }
     }
 }
@@ -1676,11 +1687,15 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
     const int64_t blocks = (tiles + kXcdSpan - 1) / kXcdSpan * kXcdSpan;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     if (a.m > kMaxLine) {
-        k_dist_global<uint16_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
+        k_dist_global<uint16_t, kLongChunk><<<(unsigned)blocks, kScanLanes, 0, s>>>(
             maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
     } else if (a.lines > kStagedMaxLines) {
-        k_dist_global<uint8_t><<<(unsigned)blocks, kScanLanes, 0, s>>>(
-            maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+        if (a.m >= kLongChunkLine && a.lines >= kLongChunkLines)
+            k_dist_global<uint8_t, kLongChunk><<<(unsigned)blocks, kScanLanes, 0, s>>>(
+                maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+        else
+            k_dist_global<uint8_t, 16><<<(unsigned)blocks, kScanLanes, 0, s>>>(
+                maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
     } else {
         // the split pass when every one of its work-groups is resident at once
         // (one round of half-length chains); otherwise 64 lines per wave
