@@ -136,6 +136,32 @@ def test_capped_lines_closed_form(pdm, orc):
         np.testing.assert_array_equal(pdm.from_device(v.dist).reshape(-1), want)
 
 
+def test_all_maps_long_lines_in_chunks(pdm, orc):
+    """The all-maps y pass with lines of 200 bricks and 2^20 of them (256
+    partitions of a 64x200x64 grid) takes the global-memory scan with 32-step
+    chunks and a ragged last chunk (200 = 6*32 + 8); its z pass (64-brick
+    lines) takes 16-step chunks.  Sampled PDMs against the oracle, and D' for
+    three TFs against the oracle's plain method: with one partition per level
+    the two are equal (Sec. 3.1)."""
+    import torch
+    vol = blocky((256, 800, 256), np.uint8, 256, seed=11, keep=0.02, cell=5)
+    n = 256
+    bounds = W.uniform_bounds(256, n)
+    say(f"[case] all maps, 200-brick y lines: shape={vol.shape} n={n}")
+    v = pdm.Volume(pdm.to_device(vol), 256, bounds)
+    v.build()
+    torch.cuda.synchronize()
+    bmin, bmax = orc.bricks(vol)
+    for p in (0, 1, 37, 128, 200, 255):
+        want = orc.dt(orc.pom_range(bmin, bmax, int(bounds[p]), int(bounds[p + 1]) - 1))
+        np.testing.assert_array_equal(pdm.from_device(v.pdms[p]), want, err_msg=f"PDM {p}")
+    for k, alpha in enumerate(tfs(256, 3, 12)[:3]):
+        v.update_tf(alpha)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pdm.from_device(v.dist), orc.full_recompute(vol, alpha, 256),
+                                      err_msg=f"D' tf {k}")
+
+
 def test_rhomin_partition(pdm, orc):
     vol = W.make_volume("c1")
     bounds = W.rhomin_bounds(256, 16, 2)
