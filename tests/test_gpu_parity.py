@@ -162,6 +162,24 @@ def test_all_maps_long_lines_in_chunks(pdm, orc):
                                       err_msg=f"D' tf {k}")
 
 
+MAX_SHAPES = [
+    # (shape zyx, dtype, levels, n, label): grids at the ABI's axis limits
+    ((3, 5, 4 * 16384), np.uint8, 256, 16, "x at the limit: 16384 bricks, 64 wave segments"),
+    ((4, 4 * 65535 - 2, 4), np.uint8, 256, 8, "y at the limit: 65535-brick lines"),
+    ((4 * 65535 - 1, 3, 5), np.uint16, 4096, 4, "z at the limit: 65535-brick lines, u16"),
+]
+
+
+@pytest.mark.parametrize("shape,dtype,levels,n,label", MAX_SHAPES, ids=[s[-1] for s in MAX_SHAPES])
+def test_grid_axis_limits(pdm, orc, shape, dtype, levels, n, label):
+    """Every output at the largest grid axis the library accepts (16384 bricks
+    along x, 65535 along y or z; one more is rejected, see the host tests):
+    the segmented x pass at its 64-segment maximum, and y/z lines whose
+    positions need the 16-bit scan table up to its last entry."""
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + n, keep=0.05, cell=7)
+    run_all(pdm, orc, vol, levels, W.uniform_bounds(levels, n), tfs(levels, 3, 21), label)
+
+
 def test_rhomin_partition(pdm, orc):
     vol = W.make_volume("c1")
     bounds = W.rhomin_bounds(256, 16, 2)
