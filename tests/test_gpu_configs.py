@@ -14,6 +14,10 @@ partitions (dense, sparse, empty); D' and D for 3 TFs, where the oracle's D'
 is the distance transform of the union of the active POMs (the union
 invariant, pinned separately); for all 200 TFs the active set against the
 oracle and D' <= D element-wise (Sec. 3.1).
+
+A 2048x2048x1100 u8 volume (4.3 GiB, past 2^32 bytes) with 64 partitions
+(4.3 GiB of PDMs): bricks in full, 3 sampled PDMs, and D' and D for one TF,
+so that voxel and map offsets beyond 32 bits are exercised.
 """
 import numpy as np
 import pytest
@@ -135,3 +139,47 @@ def test_tube_tree_1024x1024x795_u8(pdm, orc):
             np.testing.assert_array_equal(dp_gpu, orc.dt(union), err_msg=f"D' tf {k}")
             np.testing.assert_array_equal(d_gpu, orc.full_recompute(vol, alpha, L),
                                           err_msg=f"D tf {k}")
+
+
+@pytest.mark.timeout(300)
+def test_volume_over_4_gib_u8(pdm, orc):
+    import torch
+    shape = (1100, 2048, 2048)
+    say(f"[case] volume over 4 GiB: generate {shape} u8")
+    rng = np.random.default_rng(23)
+    vol = np.zeros(shape, np.uint8)
+    for _ in range(400):
+        c = [int(rng.integers(0, d)) for d in shape]
+        h = [int(rng.integers(2, 40)) for _ in shape]
+        vol[max(0, c[0] - h[0]):c[0] + h[0], max(0, c[1] - h[1]):c[1] + h[1],
+            max(0, c[2] - h[2]):c[2] + h[2]] = int(rng.integers(1, 256))
+    assert vol.nbytes > 2 ** 32
+    L, n = 256, 64
+    bounds = W.uniform_bounds(L, n)
+    say("[case] volume over 4 GiB: build on GPU")
+    v = pdm.Volume(pdm.to_device(vol), L, bounds)
+    assert v.pdm_bytes > 2 ** 32
+    v.build()
+    alpha = np.zeros(L, np.float32)
+    alpha[100:140] = 0.5
+    alpha[250] = 1.0
+    mask = v.update_tf(alpha)
+    d = torch.empty_like(v.dist)
+    v.full_recompute(alpha, out=d)
+    torch.cuda.synchronize()
+    bmin, bmax = orc.bricks(vol)
+    np.testing.assert_array_equal(pdm.from_device(v.bmin), bmin)
+    np.testing.assert_array_equal(pdm.from_device(v.bmax), bmax)
+    for p in (0, 17, 63):
+        say(f"[case] volume over 4 GiB: PDM {p}")
+        want = orc.dt(orc.pom_range(bmin, bmax, int(bounds[p]), int(bounds[p + 1]) - 1))
+        np.testing.assert_array_equal(pdm.from_device(v.pdms[p]), want, err_msg=f"PDM {p}")
+    m = orc.active(bounds, alpha, L)
+    np.testing.assert_array_equal(mask, m)
+    say("[case] volume over 4 GiB: D' and D")
+    union = np.zeros(bmin.shape, np.uint8)
+    for p in orc.active_list(m, n):
+        union |= orc.pom_range(bmin, bmax, int(bounds[p]), int(bounds[p + 1]) - 1)
+    np.testing.assert_array_equal(pdm.from_device(v.dist), orc.dt(union), err_msg="D'")
+    np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, L),
+                                  err_msg="D")
