@@ -713,8 +713,8 @@ __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol
 // Each step writes last[f(i)] = i and then reads last[F(i)+1] for the next
 // step; the read comes after the write, so it sees it.  Reading the next
 // step's candidates ahead (to keep the read off the chain between steps)
-// measured slower: the pass is bound by instructions per step, not by the
-// table's latency.
+// measured slower: the extra reads and selects cost more issue time than the
+// wait they removed.
 //
 // Tables: 258 rows (values 0..257, the last two never written) of kPitch
 // entries, lane-major inside a row; the odd dword pitch (17) spreads lanes
