@@ -417,14 +417,40 @@ __device__ __forceinline__ void store_quad(DP __restrict__ dst, int64_t idx, int
 // ---------------------------------------------------------------------------
 // k_pom_x: one wave per brick row (bz, by); 4 waves per work-group.  For
 // every partition p: POM nibble from [min,max] (RANGE reading) and the x
-// distances, written to pdms[p*G + row*Bx + x].
+// distances, written to pdms[p*G + row*Bx + x].  Rows of at most 128 bricks
+// are packed 64/W to a wave (W < 64 lanes per row, the power of two with
+// 4W >= Bx), so narrow grids keep every lane busy.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_pom_x(const T* __restrict__ bmin,
                                                const T* __restrict__ bmax, int Bx, int64_t rows,
                                                Bounds bounds, int n, uint8_t* __restrict__ pdms,
-                                               int64_t G, int store_vec) {
+                                               int64_t G, int store_vec, int W) {
     const int lane = threadIdx.x & (kWave - 1);
+    if (W < kWave) {
+        const int per = kWave / W;
+        const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * per;
+        if (row0 >= rows) return;  // wave-uniform
+        const int64_t row = row0 + lane / W;
+        const int q = lane & (W - 1);
+        const int nb = row < rows ? max(0, min(4, Bx - 4 * q)) : 0;
+        const int64_t rbase = row * Bx + 4 * q;
+        uint32_t mn[4], mx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            mn[k] = k < nb ? (uint32_t)bmin[rbase + k] : 0xFFFFFFFFu;
+            mx[k] = k < nb ? (uint32_t)bmax[rbase + k] : 0u;
+        }
+        for (int p = 0; p < n; ++p) {
+            const uint32_t lo = (uint32_t)bounds.b[p], hi = (uint32_t)bounds.b[p + 1] - 1u;
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+            const uint32_t packed = x_distances_rows(o, lane, W);
+            if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase, nb, packed, store_vec);
+        }
+        return;
+    }
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (row >= rows) return;  // wave-uniform
     const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
@@ -1592,13 +1618,15 @@ hipError_t launch_bricks(const BrickArgs& a, hipStream_t s) {
 
 hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s) {
     const int64_t rows = (int64_t)a.By * a.Bz;
-    const unsigned nb = blocks_for(rows, 4);
+    int W = 1;  // lanes per row: the power of two with 4W >= Bx, at most a wave
+    while (W < kWave && 4 * W < a.Bx) W *= 2;
+    const unsigned nb = blocks_for(rows, 4 * (kWave / W));
     if (a.bytes == 1)
         k_pom_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.bmin, (const uint8_t*)a.bmax, a.Bx,
-                                            rows, b, a.n, a.pdms, a.G, a.store_vec);
+                                            rows, b, a.n, a.pdms, a.G, a.store_vec, W);
     else
         k_pom_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.bmin, (const uint16_t*)a.bmax,
-                                             a.Bx, rows, b, a.n, a.pdms, a.G, a.store_vec);
+                                             a.Bx, rows, b, a.n, a.pdms, a.G, a.store_vec, W);
     return hipGetLastError();
 }
 
