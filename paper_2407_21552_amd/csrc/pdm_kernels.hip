@@ -629,22 +629,29 @@ __device__ __forceinline__ void quad_voxels(const T* __restrict__ vol, int nx, i
 // its 4 bricks, which partitions hold one of their voxels (NW = ceil(n/32)
 // mask words per brick, from an LDS table intensity -> partition), then the
 // wave computes every partition's x distances from those masks.  Reads the
-// volume once and writes n*G bytes.
-template <typename T, int NW>
+// volume once and writes n*G bytes.  Rows of at most 128 bricks are packed
+// 64/W to a wave (W lanes per row), as in k_pom_x.
+template <typename T, int NW, bool PACK>
 __global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, int nx, int ny,
                                                      int nz, int Bx, int By, int64_t rows,
                                                      Bounds bounds, int n, int levels,
                                                      uint8_t* __restrict__ pdms, int64_t G,
-                                                     int store_vec) {
+                                                     int store_vec, int W) {
     __shared__ uint8_t s_part[PDM_EXACT_MAX_LEVELS];
     // partition p paints its intensities [bounds[p], bounds[p+1])
     for (int p = threadIdx.x; p < n; p += blockDim.x)
         for (int v = bounds.b[p]; v < bounds.b[p + 1]; ++v) s_part[v] = (uint8_t)p;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (row >= rows) return;  // wave-uniform, after the barrier
-    const int by = (int)(row % By), bz = (int)(row / By);
+    // PACK (W < 64): rows of at most 128 bricks, 64/W to a wave (W lanes per row)
+    if (!PACK) W = kWave;
+    const int per = kWave / W;
+    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * per;
+    if (row0 >= rows) return;  // wave-uniform, after the barrier
+    const int64_t row = row0 + lane / W;
+    const int q = lane & (W - 1);  // quad index within the row
+    const bool row_ok = row < rows;
+    const int by = row_ok ? (int)(row % By) : 0, bz = row_ok ? (int)(row / By) : 0;
     const int64_t rbase = row * Bx;
     uint32_t mk[4][NW];
 #pragma unroll
@@ -652,15 +659,15 @@ __global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, 
 #pragma unroll
         for (int w = 0; w < NW; ++w) mk[k][w] = 0u;
     const uint32_t top = (uint32_t)levels - 1u;  // voxels >= levels break the precondition
-    if (4 * lane < Bx) {
-        quad_voxels<T>(vol, nx, ny, nz, lane, by, bz, [&](int k, uint32_t val) {
+    if (row_ok && 4 * q < Bx) {
+        quad_voxels<T>(vol, nx, ny, nz, q, by, bz, [&](int k, uint32_t val) {
             const uint32_t pid = s_part[umin(val, top)];
             const uint32_t bit = 1u << (pid & 31u);
 #pragma unroll
             for (int w = 0; w < NW; ++w) mk[k][w] |= ((pid >> 5) == (uint32_t)w) ? bit : 0u;
         });
     }
-    const int nb = max(0, min(4, Bx - 4 * lane));
+    const int nb = row_ok ? max(0, min(4, Bx - 4 * q)) : 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const int pend = min(32, n - 32 * w);
@@ -668,9 +675,13 @@ __global__ void __launch_bounds__(256) k_pom_exact_x(const T* __restrict__ vol, 
             uint32_t o = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) o |= ((mk[k][w] >> b) & 1u) << k;
-            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
+            uint32_t packed;
+            if constexpr (PACK)
+                packed = x_distances_rows(o, lane, W);
+            else
+                packed = x_distances(o, lane, 0, -kNone, kNone);
             if (nb > 0)
-                store_quad(pdms + (int64_t)(32 * w + b) * G, rbase + 4 * lane, nb, packed, store_vec);
+                store_quad(pdms + (int64_t)(32 * w + b) * G, rbase + 4 * q, nb, packed, store_vec);
         }
     }
 }
@@ -1647,12 +1658,21 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
 template <typename T>
 static hipError_t launch_pom_exact_t(const PomExactArgs& a, const Bounds& b, hipStream_t s) {
     const int64_t rows = (int64_t)a.By * a.Bz;
-    const unsigned nb = blocks_for(rows, 4);
+    int W = 1;  // lanes per row: the power of two with 4W >= Bx, at most a wave
+    while (W < kWave && 4 * W < a.Bx) W *= 2;
+    const unsigned nb = blocks_for(rows, 4 * (kWave / W));
     const int nw = (a.n + 31) / 32;
 #define PDM_LAUNCH_EXACT(NW)                                                                   \
-    k_pom_exact_x<T, NW><<<nb, 256, 0, s>>>((const T*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By, rows, \
-                                            b, a.n, a.levels, a.pdms, a.G,                       \
-                                            a.store_vec)
+    do {                                                                                       \
+        if (W < kWave)                                                                         \
+            k_pom_exact_x<T, NW, true><<<nb, 256, 0, s>>>((const T*)a.vol, a.nx, a.ny, a.nz,     \
+                                                          a.Bx, a.By, rows, b, a.n, a.levels,    \
+                                                          a.pdms, a.G, a.store_vec, W);          \
+        else                                                                                   \
+            k_pom_exact_x<T, NW, false><<<nb, 256, 0, s>>>((const T*)a.vol, a.nx, a.ny, a.nz,    \
+                                                           a.Bx, a.By, rows, b, a.n, a.levels,   \
+                                                           a.pdms, a.G, a.store_vec, W);         \
+    } while (0)
     if (nw == 1)
         PDM_LAUNCH_EXACT(1);
     else if (nw == 2)
