@@ -32,9 +32,10 @@
  *     and keeps no pointer after returning.  Host arrays are read during the
  *     call only and may be freed as soon as it returns.
  *   - Device work is enqueued on `stream` (0 = the null stream) and the call
- *     returns without synchronising.  There is no global state: calls are
- *     reentrant; calls that write the same buffers must be ordered by the
- *     caller (same stream or events).
+ *     returns without synchronising.  There is no global state (one
+ *     exception: pdm_batch_build_noalloc keeps its scratch in a static device
+ *     array): calls are reentrant; calls that write the same buffers must be
+ *     ordered by the caller (same stream or events).
  *   - Arguments are validated on the host before any device work; a failed
  *     check returns PDM_E_INVAL or PDM_E_UNSUPPORTED and enqueues nothing.
  *     PDM_E_DEVICE reports a failed kernel launch.
@@ -263,6 +264,26 @@ size_t pdm_batch_workspace_bytes(int32_t count);
 pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
                            size_t workspace_bytes, const pdm_batch_config* cfg,
                            hipStream_t stream);
+
+/* pdm_batch_build without a workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The descriptors and
+ * the barrier state live in a static device array of the library (57,600
+ * bytes: room for PDM_BATCH_MAX volumes, the limit of count; more is
+ * PDM_E_INVAL), one per device, held until the process ends; its address is
+ * looked up once per device on the first call.  Same validation, kernels and
+ * results as pdm_batch_build; calls nothing that allocates.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (each call rewrites the descriptors and zeroes the barrier state
+ * before its kernels run): calls on one device that overlap in time (on
+ * different streams, or from several threads without ordering) race and
+ * must not be made.  `stream` must belong to the current device
+ * (PDM_E_INVAL otherwise).  d_error: nullable device uint32; when given, the
+ * build's error word (see pdm_batch_build) is copied there on the stream
+ * after the build. */
+pdm_status pdm_batch_build_noalloc(const pdm_batch_volume* h_vols, int32_t count,
+                                   const pdm_batch_config* cfg, uint32_t* d_error,
+                                   hipStream_t stream);
 
 /* EXACT occupancy reading (Sec. 3.1, literal wording): a brick is occupied
  * for an intensity interval when one of its voxels lies in it (for the plain

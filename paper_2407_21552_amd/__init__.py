@@ -17,8 +17,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, PreparedVolume,
-                   active_set, batch_build, batch_error, batch_tf_update, batch_tf_update_prepared,
-                   batch_workspace_bytes, build_bricks, build_range_table, range_cover,
+                   active_set, batch_build, batch_build_noalloc, batch_error, batch_tf_update,
+                   batch_tf_update_prepared, batch_workspace_bytes, build_bricks, build_range_table, range_cover,
                    range_table_maps, tf_update_ranges, tf_update_ranges_prepared,
                    batch_tf_update_ranges, batch_tf_update_ranges_prepared,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
@@ -26,7 +26,8 @@ from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, Prepare
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
                    volume_desc)
 
-__all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build", "batch_error",
+__all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build",
+           "batch_build_noalloc", "batch_error",
            "batch_tf_update", "batch_tf_update_prepared", "batch_workspace_bytes", "BATCH_MAX",
            "build_bricks", "build_partitions", "build_range_table", "range_cover",
            "range_table_maps", "tf_update_ranges", "tf_update_ranges_prepared",

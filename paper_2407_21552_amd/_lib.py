@@ -102,11 +102,14 @@ def lib() -> ctypes.CDLL:
         L.pdm_batch_workspace_bytes.restype = ctypes.c_size_t
         L.pdm_batch_build.argtypes = [ctypes.POINTER(BatchVolume), i32, P, ctypes.c_size_t,
                                       ctypes.POINTER(BatchConfig), P]
+        L.pdm_batch_build_noalloc.argtypes = [ctypes.POINTER(BatchVolume), i32,
+                                              ctypes.POINTER(BatchConfig), P, P]
         for name in ("pdm_grid_of", "pdm_active_set", "pdm_build_bricks", "pdm_build_partitions",
                      "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
                      "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
                      "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
                      "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build",
+                     "pdm_batch_build_noalloc",
                      "pdm_build_range_table", "pdm_range_cover", "pdm_tf_update_ranges",
                      "pdm_batch_tf_update_ranges"):
             getattr(L, name).restype = st
@@ -562,13 +565,9 @@ def batch_workspace_bytes(count: int) -> int:
     return int(lib().pdm_batch_workspace_bytes(int(count)))
 
 
-def batch_build(items, workspace, config=None, stream=None) -> None:
-    """Bricks and PDMs of several volumes in three grouped launches.
-    items: sequence of (desc, volume, bmin, bmax, bounds, pdms); workspace: a
-    uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more
-    (it receives the descriptors; keep it until the stream has passed);
-    config: None or dict(rows_per_item=, lines_mult=, largest_first=,
-    single_launch=)."""
+def _batch_volumes(items):
+    """pdm_batch_volume rows for (desc, volume, bmin, bmax, bounds, pdms)
+    items, and the host objects they point to (keep them alive)."""
     count = len(items)
     if not 1 <= count <= BATCH_MAX:
         raise ValueError(f"a batch holds 1..{BATCH_MAX} volumes, got {count}")
@@ -586,18 +585,46 @@ def batch_build(items, workspace, config=None, stream=None) -> None:
         arr[k].h_bounds = _np_ptr(b)
         arr[k].n = n
         arr[k].d_pdms = _dev_ptr(pdms, n * G, "pdms")
+    return arr, keep
+
+
+def _batch_config(config):
+    if config is None:
+        return None
+    return ctypes.pointer(BatchConfig(int(config.get("rows_per_item", 0)),
+                                      int(config.get("lines_mult", 0)),
+                                      int(config.get("largest_first", 0)),
+                                      int(config.get("single_launch", 0))))
+
+
+def batch_build(items, workspace, config=None, stream=None) -> None:
+    """Bricks and PDMs of several volumes in three grouped launches.
+    items: sequence of (desc, volume, bmin, bmax, bounds, pdms); workspace: a
+    uint8 device tensor of batch_workspace_bytes(len(items)) bytes or more
+    (it receives the descriptors; keep it until the stream has passed);
+    config: None or dict(rows_per_item=, lines_mult=, largest_first=,
+    single_launch=)."""
+    arr, keep = _batch_volumes(items)
+    count = len(items)
     need = batch_workspace_bytes(count)
     ws_bytes = workspace.numel() * workspace.element_size()
     if ws_bytes < need:
         raise ValueError(f"workspace holds {ws_bytes} bytes, needs {need}")
-    cfg = None
-    if config is not None:
-        cfg = ctypes.pointer(BatchConfig(int(config.get("rows_per_item", 0)),
-                                         int(config.get("lines_mult", 0)),
-                                         int(config.get("largest_first", 0)),
-                                         int(config.get("single_launch", 0))))
     _check(lib().pdm_batch_build(arr, count, _dev_ptr(workspace, ws_bytes, "workspace"),
-                                 ws_bytes, cfg, _stream(stream)), "pdm_batch_build")
+                                 ws_bytes, _batch_config(config), _stream(stream)),
+           "pdm_batch_build")
+    del keep
+
+
+def batch_build_noalloc(items, config=None, error=None, stream=None) -> None:
+    """batch_build without a workspace: the library's static device array
+    holds the descriptors and barrier state, nothing is allocated.  Calls on
+    one device must not overlap in time.  error: None or a device tensor of
+    4 bytes that receives the build's error word."""
+    arr, keep = _batch_volumes(items)
+    err = ctypes.c_void_p(0) if error is None else _dev_ptr(error, 4, "error")
+    _check(lib().pdm_batch_build_noalloc(arr, len(items), _batch_config(config), err,
+                                         _stream(stream)), "pdm_batch_build_noalloc")
     del keep
 
 

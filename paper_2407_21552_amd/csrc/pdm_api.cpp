@@ -411,13 +411,15 @@ size_t pdm_batch_workspace_bytes(int32_t count) {
     return sizeof(pdm::BatchSync) + (size_t)count * sizeof(pdm::BatchVol);
 }
 
-pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
-                           size_t workspace_bytes, const pdm_batch_config* cfg,
-                           hipStream_t stream) {
-    if (h_vols == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
-    if (d_workspace == nullptr || !aligned(d_workspace, 16) ||
-        workspace_bytes < pdm_batch_workspace_bytes(count))
-        return PDM_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// Validation and descriptor packing shared by both batched-build entry
+// points (host only, no HIP call): vols[0..count) in launch order, the item
+// totals per phase and the configuration with defaults filled in.
+pdm_status batch_prepare(const pdm_batch_volume* h_vols, int32_t count, const pdm_batch_config* cfg,
+                         pdm::BatchVol* vols, int64_t totals[3], pdm_batch_config* out_cfg) {
     pdm_batch_config c = {0, 0, 0, 0};
     if (cfg != nullptr) c = *cfg;
     if (c.rows_per_item < 0 || c.rows_per_item > 256 || c.lines_mult < 0 || c.lines_mult > 16 ||
@@ -425,9 +427,7 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         return PDM_E_INVAL;
     if (c.lines_mult == 0) c.lines_mult = 1;
     if (c.rows_per_item == 0) c.rows_per_item = 2;
-    // host staging of the descriptors (copied to the workspace by the launcher)
     pdm::BatchVol tmp[PDM_BATCH_MAX];
-    pdm::BatchVol vols[PDM_BATCH_MAX];
     int64_t work[PDM_BATCH_MAX];
     for (int32_t k = 0; k < count; ++k) {
         const pdm_batch_volume& it = h_vols[k];
@@ -483,7 +483,7 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
                 order[b - 1] = t;
             }
     for (int32_t k = 0; k < count; ++k) vols[k] = tmp[order[k]];
-    int64_t totals[3] = {0, 0, 0};
+    totals[0] = totals[1] = totals[2] = 0;
     for (int ph = 0; ph < 3; ++ph)
         for (int32_t k = 0; k < count; ++k) {
             vols[k].first[ph] = totals[ph];
@@ -491,11 +491,60 @@ pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* 
         }
     for (int ph = 0; ph < 3; ++ph)
         if (totals[ph] > INT32_MAX - 64) return PDM_E_UNSUPPORTED;
+    *out_cfg = c;
+    return PDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdm_status pdm_batch_build(const pdm_batch_volume* h_vols, int32_t count, void* d_workspace,
+                           size_t workspace_bytes, const pdm_batch_config* cfg,
+                           hipStream_t stream) {
+    if (h_vols == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
+    if (d_workspace == nullptr || !aligned(d_workspace, 16) ||
+        workspace_bytes < pdm_batch_workspace_bytes(count))
+        return PDM_E_INVAL;
+    pdm::BatchVol vols[PDM_BATCH_MAX];
+    int64_t totals[3];
+    pdm_batch_config c;
+    const pdm_status st = batch_prepare(h_vols, count, cfg, vols, totals, &c);
+    if (st != PDM_OK) return st;
     uint8_t* ws = static_cast<uint8_t*>(d_workspace);
     pdm::BatchSync* sync = reinterpret_cast<pdm::BatchSync*>(ws);
     pdm::BatchVol* dv = reinterpret_cast<pdm::BatchVol*>(ws + sizeof(pdm::BatchSync));
     return from_hip(pdm::launch_batch_build(vols, count, dv, sync, totals, c.lines_mult,
                                             c.single_launch, stream));
+}
+
+pdm_status pdm_batch_build_noalloc(const pdm_batch_volume* h_vols, int32_t count,
+                                   const pdm_batch_config* cfg, uint32_t* d_error,
+                                   hipStream_t stream) {
+    if (h_vols == nullptr || count < 1 || count > PDM_BATCH_MAX) return PDM_E_INVAL;
+    pdm::BatchVol vols[PDM_BATCH_MAX];
+    int64_t totals[3];
+    pdm_batch_config c;
+    const pdm_status st = batch_prepare(h_vols, count, cfg, vols, totals, &c);
+    if (st != PDM_OK) return st;
+    // the scratch array of the current device; the stream must belong to it
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PDM_E_DEVICE;
+    if (stream != nullptr) {
+        int sdev = -1;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return PDM_E_DEVICE;
+        if (sdev != dev) return PDM_E_INVAL;
+    }
+    uint8_t* ws = nullptr;
+    size_t cap = 0;
+    if (pdm::batch_scratch(dev, &ws, &cap) != hipSuccess) return PDM_E_DEVICE;
+    if (cap < pdm_batch_workspace_bytes(count)) return PDM_E_UNSUPPORTED;
+    pdm::BatchSync* sync = reinterpret_cast<pdm::BatchSync*>(ws);
+    pdm::BatchVol* dv = reinterpret_cast<pdm::BatchVol*>(ws + sizeof(pdm::BatchSync));
+    hipError_t e = pdm::launch_batch_build(vols, count, dv, sync, totals, c.lines_mult,
+                                           c.single_launch, stream);
+    if (e == hipSuccess && d_error != nullptr) e = pdm::launch_copy_word(&sync->error, d_error, stream);
+    return from_hip(e);
 }
 
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,

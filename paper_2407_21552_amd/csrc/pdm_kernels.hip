@@ -34,6 +34,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "pdm_launch.h"
 
 namespace pdm {
@@ -1602,6 +1604,46 @@ __global__ void __launch_bounds__(256) k_upload(uint8_t* __restrict__ dst, Uploa
 
 __global__ void __launch_bounds__(256) k_zero(uint32_t* __restrict__ p, int words) {
     for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(64) k_copy_word(const uint32_t* __restrict__ src,
+                                                  uint32_t* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free batched build: the barrier state and the
+// descriptors of up to PDM_BATCH_MAX_ITEMS volumes, laid out as the caller's
+// workspace of the other entry point (57,600 bytes).  Each device holds its
+// own copy for the life of the process.  In host code `scratch` only names
+// the symbol: its device address comes from hipGetSymbolAddress, looked up
+// once per device with that device current and kept here.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = sizeof(BatchSync) + (size_t)PDM_BATCH_MAX_ITEMS * sizeof(BatchVol);
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t* g_scratch_ptr[kScratchDevices];
+
+hipError_t batch_scratch(int dev, uint8_t** ptr, size_t* bytes) {
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<uint8_t*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    *bytes = kScratchBytes;
+    return hipSuccess;
+}
+
+hipError_t launch_copy_word(const uint32_t* src, uint32_t* dst, hipStream_t s) {
+    k_copy_word<<<1, 64, 0, s>>>(src, dst);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -152,6 +152,12 @@ hipError_t launch_batch_maps(BatchMapsArgs& a, hipStream_t s);
 hipError_t launch_batch_build(const BatchVol* h_vols, int count, BatchVol* d_vols,
                               BatchSync* d_sync, const int64_t totals[3], int lines_mult,
                               int single, hipStream_t s);
+// Device address and size of the calling device's scratch array of the
+// allocation-free batched build (dev must be the current device); looked up
+// on the first call per device.
+hipError_t batch_scratch(int dev, uint8_t** ptr, size_t* bytes);
+// *dst = *src (one word, device memory), on the stream.
+hipError_t launch_copy_word(const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t launch_distance_yz(uint8_t* maps, int count, int Bx, int By, int Bz, hipStream_t s);
 // out = element-wise min of the listed maps of G bytes (255 for none); any
 // size and pointer alignment.
