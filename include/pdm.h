@@ -178,6 +178,18 @@ pdm_status pdm_tf_update_ranges(const pdm_volume* v, const uint8_t* d_pdms, cons
 pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                               uint8_t* d_dist, hipStream_t stream);
 
+/* Plain method from the cached brick [min, max] instead of the volume: the
+ * same occupancy test as pdm_full_recompute (some intensity i in
+ * [bmin, bmax] has h_alpha[i] != 0) and the same D, but reading 2*G*s bytes
+ * of brick ranges instead of the whole volume.  This is the comparator that
+ * an implementation of the plain method (Sec. 2, Sec. 4.2) keeping the
+ * brick ranges of the one-time initialisation would run per TF change.
+ * d_bmin/d_bmax: output of pdm_build_bricks (G elements of v->dtype each).
+ * levels <= PDM_MAX_PLAIN_LEVELS.  d_dist: G bytes.  Equivalent to
+ * pdm_plain_cached_distance_x followed by pdm_distance_yz(count = 1). */
+pdm_status pdm_full_recompute_cached(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                                     const float* h_alpha, uint8_t* d_dist, hipStream_t stream);
+
 /* Batched TF update: the update of pdm_tf_update for up to PDM_BATCH_MAX
  * volumes, each with its own PDMs, partitions, opacity table and output, in
  * one kernel launch (the step a server runs per tick).  h_items: `count`
@@ -321,6 +333,11 @@ pdm_status pdm_pom_distance_x(const pdm_volume* v, const void* d_bmin, const voi
  * volume and the distance to the nearest occupied brick along x only. */
 pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const float* h_alpha,
                                 uint8_t* d_dist, hipStream_t stream);
+
+/* First phase of pdm_full_recompute_cached: brick occupancy under the TF
+ * from the cached [min, max] and the distance along x only. */
+pdm_status pdm_plain_cached_distance_x(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                                       const float* h_alpha, uint8_t* d_dist, hipStream_t stream);
 
 /* First phase of pdm_build_partitions_exact: EXACT POMs and x distances. */
 pdm_status pdm_pom_exact_distance_x(const pdm_volume* v, const void* d_volume,

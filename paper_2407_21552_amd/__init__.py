@@ -22,7 +22,7 @@ from ._lib import (BATCH_MAX, BRICK, DIST_CAP, MAX_PARTITIONS, PdmError, Prepare
                    range_table_maps, tf_update_ranges, tf_update_ranges_prepared,
                    batch_tf_update_ranges, batch_tf_update_ranges_prepared,
                    build_partitions, build_partitions_exact, distance_yz, full_recompute,
-                   full_recompute_exact, grid_of, mask_to_list, plain_distance_x,
+                   full_recompute_cached, full_recompute_exact, plain_cached_distance_x, grid_of, mask_to_list, plain_distance_x,
                    plain_exact_distance_x, pom_distance_x, pom_exact_distance_x, tf_update,
                    volume_desc)
 
@@ -32,7 +32,8 @@ __all__ = ["Volume", "PdmError", "PreparedVolume", "active_set", "batch_build",
            "build_bricks", "build_partitions", "build_range_table", "range_cover",
            "range_table_maps", "tf_update_ranges", "tf_update_ranges_prepared",
            "batch_tf_update_ranges", "batch_tf_update_ranges_prepared",
-           "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_exact",
+           "build_partitions_exact", "distance_yz", "full_recompute", "full_recompute_cached",
+           "full_recompute_exact", "plain_cached_distance_x",
            "grid_of", "mask_to_list", "plain_distance_x", "plain_exact_distance_x",
            "pom_distance_x", "pom_exact_distance_x", "tf_update", "volume_desc", "BRICK",
            "DIST_CAP", "MAX_PARTITIONS", "to_device", "from_device", "RANGE", "EXACT"]
@@ -140,3 +141,11 @@ class Volume:
         """Plain method: D from the raw volume."""
         fn = full_recompute_exact if self.mode == EXACT else full_recompute
         fn(self.desc, self.volume, alpha, self.dist if out is None else out, stream)
+
+    def full_recompute_cached(self, alpha, out=None, stream=None) -> None:
+        """Plain method from the cached brick [min, max] (RANGE reading; call
+        after build()): the same D as full_recompute."""
+        if self.mode != RANGE:
+            raise ValueError("the cached-range plain method exists in the RANGE reading only")
+        full_recompute_cached(self.desc, self.bmin, self.bmax, alpha,
+                              self.dist if out is None else out, stream)

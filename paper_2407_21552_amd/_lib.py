@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.pdm_build_partitions.argtypes = [V, P, P, P, i32, P, P]
         L.pdm_tf_update.argtypes = [V, P, P, i32, P, P, P, P]
         L.pdm_full_recompute.argtypes = [V, P, P, P, P]
+        L.pdm_full_recompute_cached.argtypes = [V, P, P, P, P, P]
+        L.pdm_plain_cached_distance_x.argtypes = [V, P, P, P, P, P]
         L.pdm_pom_distance_x.argtypes = [V, P, P, P, i32, P, P]
         L.pdm_plain_distance_x.argtypes = [V, P, P, P, P]
         L.pdm_distance_yz.argtypes = [V, P, i32, P]
@@ -106,6 +108,7 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(BatchConfig), P, P]
         for name in ("pdm_grid_of", "pdm_active_set", "pdm_build_bricks", "pdm_build_partitions",
                      "pdm_tf_update", "pdm_full_recompute", "pdm_pom_distance_x",
+                     "pdm_full_recompute_cached", "pdm_plain_cached_distance_x",
                      "pdm_plain_distance_x", "pdm_distance_yz", "pdm_build_partitions_exact",
                      "pdm_pom_exact_distance_x", "pdm_full_recompute_exact",
                      "pdm_plain_exact_distance_x", "pdm_batch_tf_update", "pdm_batch_build",
@@ -327,6 +330,27 @@ def full_recompute(desc, volume, alpha, dist, stream=None) -> None:
     _check(lib().pdm_full_recompute(ctypes.byref(desc), _dev_ptr(volume, _vox_bytes(desc), "volume"),
                                     _np_ptr(a), _dev_ptr(dist, G, "dist"), _stream(stream)),
            "pdm_full_recompute")
+
+
+def full_recompute_cached(desc, bmin, bmax, alpha, dist, stream=None) -> None:
+    """Plain method from the cached brick [min, max] (pdm_build_bricks'
+    output): the same D as full_recompute without reading the volume."""
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_full_recompute_cached(ctypes.byref(desc), _dev_ptr(bmin, G * desc.dtype, "bmin"),
+                                           _dev_ptr(bmax, G * desc.dtype, "bmax"), _np_ptr(a),
+                                           _dev_ptr(dist, G, "dist"), _stream(stream)),
+           "pdm_full_recompute_cached")
+
+
+def plain_cached_distance_x(desc, bmin, bmax, alpha, dist, stream=None) -> None:
+    G = grid_of(desc)[3]
+    a = _alpha(alpha, desc.levels)
+    _check(lib().pdm_plain_cached_distance_x(ctypes.byref(desc),
+                                             _dev_ptr(bmin, G * desc.dtype, "bmin"),
+                                             _dev_ptr(bmax, G * desc.dtype, "bmax"), _np_ptr(a),
+                                             _dev_ptr(dist, G, "dist"), _stream(stream)),
+           "pdm_plain_cached_distance_x")
 
 
 def plain_distance_x(desc, volume, alpha, dist, stream=None) -> None:

@@ -563,6 +563,36 @@ pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const f
     return pdm_distance_yz(v, d_dist, 1, stream);
 }
 
+pdm_status pdm_plain_cached_distance_x(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                                       const float* h_alpha, uint8_t* d_dist, hipStream_t stream) {
+    if (d_bmin == nullptr || d_bmax == nullptr) return PDM_E_INVAL;
+    pdm::PlainArgs pa;
+    AlphaBits bits;
+    // the bitmap and the geometry as for the plain method (d_bmin stands in
+    // for the volume pointer in the shared checks)
+    const pdm_status st = plain_args(v, d_bmin, h_alpha, d_dist, &pa, &bits);
+    if (st != PDM_OK) return st;
+    pdm::CachedArgs a;
+    a.bmin = d_bmin;
+    a.bmax = d_bmax;
+    a.dist = d_dist;
+    a.Bx = pa.Bx;
+    a.By = pa.By;
+    a.Bz = pa.Bz;
+    a.bytes = pa.bytes;
+    a.nwords = pa.nwords;
+    a.levels = pa.levels;
+    a.store_vec = pa.store_vec;
+    return from_hip(pdm::launch_plain_cached_x(a, bits, stream));
+}
+
+pdm_status pdm_full_recompute_cached(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
+                                     const float* h_alpha, uint8_t* d_dist, hipStream_t stream) {
+    pdm_status st = pdm_plain_cached_distance_x(v, d_bmin, d_bmax, h_alpha, d_dist, stream);
+    if (st != PDM_OK) return st;
+    return pdm_distance_yz(v, d_dist, 1, stream);
+}
+
 pdm_status pdm_pom_exact_distance_x(const pdm_volume* v, const void* d_volume,
                                     const int32_t* h_bounds, int32_t n, uint8_t* d_pdms,
                                     hipStream_t stream) {

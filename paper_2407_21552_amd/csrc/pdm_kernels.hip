@@ -574,6 +574,69 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 }
 
 // ---------------------------------------------------------------------------
+// Plain method from the cached brick [min,max] (the volume is not read): the
+// same occupancy test as k_plain_x on bmin/bmax, then the x distances.  The
+// row layout follows k_pom_x: rows of at most 128 bricks packed 64/W to a
+// wave, one wave per row up to 256 bricks, 256-brick segments beyond.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_plain_cached_x(const T* __restrict__ bmin,
+                                                        const T* __restrict__ bmax, int Bx,
+                                                        int64_t rows, AlphaBits bits, int nwords,
+                                                        int levels, uint8_t* __restrict__ dist,
+                                                        int store_vec, int W) {
+    __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
+    __shared__ uint16_t s_pre[PDM_ALPHA_WORDS + 1];
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
+    for (int i = threadIdx.x; i <= nwords; i += blockDim.x) s_pre[i] = bits.pre[i];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t top = (uint32_t)levels - 1u;
+    // occupancy nibble of bricks x0 .. x0+3 of the row starting at rbase
+    auto nibble = [&](int64_t rbase, int x0, int nb) -> uint32_t {
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nb && any_bit(s_words, s_pre, umin((uint32_t)bmin[rbase + x0 + k], top),
+                                  umin((uint32_t)bmax[rbase + x0 + k], top)))
+                o |= 1u << k;
+        return o;
+    };
+    if (W < kWave) {
+        const int per = kWave / W;
+        const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * per;
+        if (row0 >= rows) return;  // wave-uniform
+        const int64_t row = row0 + lane / W;
+        const int q = lane & (W - 1);
+        const int nb = row < rows ? max(0, min(4, Bx - 4 * q)) : 0;
+        const int64_t rbase = row * Bx;
+        const uint32_t packed = x_distances_rows(nibble(rbase, 4 * q, nb), lane, W);
+        if (nb > 0) store_quad(dist, rbase + 4 * q, nb, packed, store_vec);
+        return;
+    }
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (row >= rows) return;  // wave-uniform
+    const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
+    const int64_t rbase = row * Bx;
+    auto seg_nibble = [&](int seg) -> uint32_t {
+        const int x = seg * kSegBricks + 4 * lane;
+        return nibble(rbase, x, max(0, min(4, Bx - x)));
+    };
+    int prev_last = -kNone;
+    uint32_t cur = seg_nibble(0);
+    for (int s = 0; s < nseg; ++s) {
+        const int xs = s * kSegBricks;
+        const uint32_t nxt = (s + 1 < nseg) ? seg_nibble(s + 1) : 0u;
+        const int next_first = (s + 1 < nseg) ? seg_first(nxt, xs + kSegBricks) : kNone;
+        const uint32_t packed = x_distances(cur, lane, xs, prev_last, next_first);
+        const int nb = max(0, min(4, Bx - xs - 4 * lane));
+        if (nb > 0) store_quad(dist, rbase + xs + 4 * lane, nb, packed, store_vec);
+        prev_last = seg_last(cur, xs);
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // EXACT occupancy (a brick is occupied when one of its voxels qualifies, the
 // literal POM wording of Sec. 3.1), for the PDM build and the plain method.
 // ---------------------------------------------------------------------------
@@ -1694,6 +1757,23 @@ hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t
         k_plain_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                                a.By, rows, bits, a.nwords, a.levels, a.dist,
                                                a.store_vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_cached_x(const CachedArgs& a, const AlphaBits& bits, hipStream_t s) {
+    const int64_t rows = (int64_t)a.By * a.Bz;
+    int W = 1;  // lanes per row: the power of two with 4W >= Bx, at most a wave
+    while (W < kWave && 4 * W < a.Bx) W *= 2;
+    const int64_t blocks = (rows + 4 * (kWave / W) - 1) / (4 * (kWave / W));
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (a.bytes == 1)
+        k_plain_cached_x<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(
+            (const uint8_t*)a.bmin, (const uint8_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
+            a.dist, a.store_vec, W);
+    else
+        k_plain_cached_x<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(
+            (const uint16_t*)a.bmin, (const uint16_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
+            a.dist, a.store_vec, W);
     return hipGetLastError();
 }
 

@@ -129,6 +129,14 @@ struct PlainArgs {
     int store_vec;
 };
 
+struct CachedArgs {
+    const void* bmin;
+    const void* bmax;
+    uint8_t* dist;
+    int Bx, By, Bz, bytes, nwords, levels;
+    int store_vec;
+};
+
 struct PomExactArgs {
     const void* vol;
     uint8_t* pdms;
@@ -140,6 +148,7 @@ struct PomExactArgs {
 hipError_t launch_bricks(const BrickArgs& a, hipStream_t s);
 hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
+hipError_t launch_plain_cached_x(const CachedArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_pom_exact_x(const PomExactArgs& a, const Bounds& b, hipStream_t s);
 hipError_t launch_plain_exact_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s);
 hipError_t launch_batch_combine(BatchArgs& a, hipStream_t s);

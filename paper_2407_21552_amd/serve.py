@@ -36,7 +36,10 @@ class VolumeSpec:
     dtype: object         # np.uint8 or np.uint16
     levels: int
     bounds: np.ndarray    # n+1 partition borders
-    load: Callable[[], np.ndarray]  # returns the voxels (host)
+    # returns the voxels on the host: a numpy array, or a pinned torch tensor
+    # (uint8, or int16 holding uint16 bits) that admission copies to the
+    # device without blocking the serving loop
+    load: Callable[[], object]
 
     @property
     def n(self) -> int:
@@ -77,8 +80,8 @@ class Executor:
         raise NotImplementedError
 
     def per_volume_limit(self) -> Optional[int]:
-        """Most requests of one volume that one launch may hold (None: no
-        limit)."""
+        """Most requests of one volume that may be launched and not yet
+        retired at any time, over all launches in flight (None: no limit)."""
         return None
 
     def launch(self, batch: List[tuple]):
@@ -92,8 +95,12 @@ class Executor:
 
 class Server:
     def __init__(self, executor: Executor, catalog: Dict[int, VolumeSpec], budget_bytes: int,
-                 max_slots: int = 24, max_batch: int = 48, clock=time.perf_counter):
+                 max_slots: int = 24, max_batch: int = 48, clock=time.perf_counter,
+                 on_complete: Optional[Callable[[Request], None]] = None):
         self.ex = executor
+        # called for every request as it is retired, before any later launch
+        # is issued (the moment its output is known to hold its result)
+        self.on_complete = on_complete
         self.catalog = catalog
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
@@ -168,6 +175,8 @@ class Server:
                     r.done = t
                     self.busy[r.vol_id] -= 1
                     self.completed.append(r)
+                    if self.on_complete is not None:
+                        self.on_complete(r)
             else:
                 still.append((ticket, reqs))
         self.inflight = still
@@ -176,16 +185,19 @@ class Server:
         """Retire finished launches, admit volumes for queued requests, and
         launch one batch of ready requests, taken in arrival order.  The scan
         stops once the batch is full, so a long queue costs no more per tick
-        than the requests it skips (volume not ready, or its per-launch
-        limit reached).  Returns the batch size."""
+        than the requests it skips (volume not ready, or its limit of
+        requests in flight reached).  Returns the batch size."""
         self._retire()
         batch, skipped = [], self._skipped
-        per_vol = collections.Counter()
         limit = self.ex.per_volume_limit()
         q = self.queue
         while q and len(batch) < self.max_batch:
             r = q.popleft()
-            if limit is not None and per_vol[r.vol_id] >= limit:
+            # at most `limit` requests of a volume launched and not yet
+            # retired, counting this batch (busy is raised as requests join
+            # it): the executor's per-volume resources (output maps) are
+            # never handed to a request while an earlier holder is in flight
+            if limit is not None and self.busy[r.vol_id] >= limit:
                 skipped.append(r)
                 continue
             h = self._ensure(r.vol_id)
@@ -198,7 +210,6 @@ class Server:
                 # counted busy at once, so a later admission in this tick
                 # cannot evict this volume
                 self.busy[r.vol_id] += 1
-                per_vol[r.vol_id] += 1
                 batch.append((h, r.alpha, r))
         q.extendleft(reversed(skipped))
         skipped.clear()
@@ -267,9 +278,11 @@ class GpuExecutor(Executor):
     table) on `admit_stream`; updates run on `update_stream`, one batched
     launch per tick (with `range_level`: the batched update through the
     tables).  Each request gets an output map from a per-volume pool of
-    `outputs_per_volume` buffers, used in turn: a result stays valid until
-    that many later requests of the same volume have been launched, and one
-    launch holds at most that many requests of a volume."""
+    `outputs_per_volume` buffers, used in turn, and at most that many
+    requests of a volume are in flight at once (the server's per-volume
+    limit), so a buffer is handed out again only after its previous request
+    has been retired: a result stays valid from its completion until that
+    many later requests of the same volume have been launched."""
 
     def __init__(self, outputs_per_volume: int = 8, keep_volume: bool = False,
                  range_level: Optional[int] = None):
@@ -303,7 +316,13 @@ class GpuExecutor(Executor):
         h.is_ready = False
         vox = spec.load()
         with torch.cuda.stream(self.admit_stream):
-            h.vol = pdm.Volume(pdm.to_device(vox), spec.levels, spec.bounds, voxel_dtype=spec.dtype)
+            if isinstance(vox, torch.Tensor):
+                # pinned host voxels: an asynchronous copy on the admission
+                # stream, ordered before the build on the same stream
+                dev = vox.to("cuda", non_blocking=True)
+            else:
+                dev = pdm.to_device(vox)
+            h.vol = pdm.Volume(dev, spec.levels, spec.bounds, voxel_dtype=spec.dtype)
             h.vol.build(self.admit_stream)
             if self.range_level:
                 h.vol.build_range_table(self.range_level, self.admit_stream)

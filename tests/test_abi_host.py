@@ -79,6 +79,11 @@ def test_null_pointers_rejected(lib):
     assert lib.pdm_tf_update(r(d), FAKE, pb, 8, NULL, FAKE, NULL, NULL) == L.PDM_E_INVAL
     assert lib.pdm_full_recompute(r(d), FAKE, pa, NULL, NULL) == L.PDM_E_INVAL
     assert lib.pdm_full_recompute(r(d), FAKE, NULL, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute_cached(r(d), NULL, FAKE, pa, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute_cached(r(d), FAKE, NULL, pa, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute_cached(r(d), FAKE, FAKE, NULL, FAKE, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_full_recompute_cached(r(d), FAKE, FAKE, pa, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_plain_cached_distance_x(r(d), NULL, FAKE, pa, FAKE, NULL) == L.PDM_E_INVAL
     assert lib.pdm_distance_yz(r(d), NULL, 1, NULL) == L.PDM_E_INVAL
     assert lib.pdm_distance_yz(r(d), FAKE, 0, NULL) == L.PDM_E_INVAL
     assert lib.pdm_distance_yz(r(d), FAKE, 257, NULL) == L.PDM_E_INVAL
@@ -107,6 +112,9 @@ def test_plain_method_rejects_too_many_levels(lib):
     alpha = np.ones(16385, np.float32)
     assert lib.pdm_full_recompute(ctypes.byref(d), FAKE, ctypes.c_void_p(alpha.ctypes.data),
                                   FAKE, NULL) == L.PDM_E_UNSUPPORTED
+    assert lib.pdm_full_recompute_cached(ctypes.byref(d), FAKE, FAKE,
+                                         ctypes.c_void_p(alpha.ctypes.data), FAKE,
+                                         NULL) == L.PDM_E_UNSUPPORTED
 
 
 def test_active_set_matches_oracle(orc):
@@ -212,6 +220,15 @@ def test_batch_build_validation(lib):
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_rows, NULL) == L.PDM_E_INVAL
     bad_mode = ctypes.pointer(L.BatchConfig(0, 1, 0, 2))
     assert lib.pdm_batch_build(arr, 1, FAKE, need, bad_mode, NULL) == L.PDM_E_INVAL
+
+    # the allocation-free variant validates the same way, before any HIP call
+    assert lib.pdm_batch_build_noalloc(arr, 0, None, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_build_noalloc(arr, 49, None, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_build_noalloc(None, 1, None, NULL, NULL) == L.PDM_E_INVAL
+    assert lib.pdm_batch_build_noalloc(arr2, 1, None, NULL, NULL) == L.PDM_E_UNSUPPORTED
+    assert lib.pdm_batch_build_noalloc(arr, 1, bad_cfg, NULL, NULL) == L.PDM_E_INVAL
+    nulls = (L.BatchVolume * 1)(L.BatchVolume(ctypes.pointer(d), FAKE, NULL, FAKE, pb, 8, FAKE))
+    assert lib.pdm_batch_build_noalloc(nulls, 1, None, NULL, NULL) == L.PDM_E_INVAL
 
 
 def _level_first(n, k):

@@ -50,10 +50,12 @@ def run_all(pdm, orc, vol, levels, bounds, alphas, label):
     want = orc.pdms(vol, bounds, levels, brick_minmax=(bmin, bmax))
     np.testing.assert_array_equal(pdm.from_device(v.pdms), want)
     d = torch.empty_like(v.dist)
+    dc = torch.empty_like(v.dist)
     for k, alpha in enumerate(alphas):
         mask = v.update_tf(alpha)
         if levels <= 16384:
             v.full_recompute(alpha, out=d)
+            v.full_recompute_cached(alpha, out=dc)
         torch.cuda.synchronize()
         dp, m = orc.tf_update(want, bounds, alpha, levels)
         np.testing.assert_array_equal(mask, m)
@@ -61,6 +63,10 @@ def run_all(pdm, orc, vol, levels, bounds, alphas, label):
         if levels <= 16384:
             np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, levels),
                                           err_msg=f"D tf {k}")
+            # plain method from the cached brick ranges: occupancy of the
+            # oracle's bricks under the TF, then its distance transform
+            want_c = orc.dt(orc.plain_occ_range(bmin, bmax, alpha, levels))
+            np.testing.assert_array_equal(pdm.from_device(dc), want_c, err_msg=f"D cached tf {k}")
     return v
 
 

@@ -162,21 +162,34 @@ def test_max_batch_and_poisson_schedule(orc):
 
 
 class LimitedExecutor(OracleExecutor):
-    """An executor whose launches hold at most `limit` requests of a volume
-    (as the GPU executor's pool of output maps)."""
+    """An executor with at most `limit` requests of a volume in flight (as
+    the GPU executor's pool of output maps), whose launches stay in flight
+    for `delay` ticks.  It records the most requests of one volume ever in
+    flight, counted as the GPU pool would see them: launched and not yet
+    retired by the server."""
 
-    def __init__(self, orc, limit):
-        super().__init__(orc)
+    def __init__(self, orc, limit, delay=0):
+        super().__init__(orc, delay)
         self.limit = limit
+        self.server = None
+        self.peak = 0
 
     def per_volume_limit(self):
         return self.limit
+
+    def launch(self, batch):
+        ticket = super().launch(batch)
+        unretired = collections.Counter(r.vol_id for _, reqs in self.server.inflight for r in reqs)
+        unretired.update(req.vol_id for _, _, req in batch)
+        self.peak = max(self.peak, max(unretired.values()))
+        return ticket
 
 
 def test_per_volume_limit_keeps_arrival_order(orc):
     cat = catalog(3)
     ex = LimitedExecutor(orc, limit=2)
     srv = Server(ex, cat, budget_bytes=10**9, max_batch=8)
+    ex.server = srv
     rng = np.random.default_rng(6)
     vols = [0, 0, 0, 1, 0, 2, 1, 1, 1, 0]
     for i, (v, a) in enumerate(zip(vols, tfs(rng, len(vols)))):
@@ -219,3 +232,28 @@ def test_pooled_poisson_tfs_are_shared():
         assert alpha.shape == ({0: 256, 1: 4096}[v],)
         ids[v].add(id(alpha))
     assert all(len(s) <= 4 for s in ids.values())
+
+
+def test_per_volume_limit_counts_requests_in_flight(orc):
+    """The limit covers every launch still in flight, not only the one being
+    formed: a pool of `limit` output maps per volume is never handed to a
+    request while an earlier request holding the same map is unretired."""
+    cat = catalog(2)
+    ex = LimitedExecutor(orc, limit=2, delay=4)
+    done_at_retire = {}
+    srv = Server(ex, cat, budget_bytes=10**9, max_batch=8,
+                 on_complete=lambda r: done_at_retire.setdefault(r.req_id, r.done))
+    ex.server = srv
+    rng = np.random.default_rng(10)
+    a = tfs(rng, 24)
+    for i in range(24):
+        srv.submit(Request(i, 0 if i % 3 else 1, a[i], 0.0))
+        srv.tick()                        # launches overlap: each stays in flight 4 ticks
+    srv.drain()
+    assert len(srv.completed) == 24
+    assert ex.peak == 2
+    assert sorted(done_at_retire) == list(range(24))
+    for r in srv.completed:
+        spec = cat[r.vol_id]
+        want = orc.tf_update(orc.pdms(spec.load(), spec.bounds, 256), spec.bounds, r.alpha, 256)[0]
+        np.testing.assert_array_equal(r.result, want)

@@ -372,13 +372,17 @@ def make_tfs(name: str, count=None):
 
 
 def poisson_requests(rate_hz: float, seconds: float, vol_ids, levels_of, ramps=(1, 4), seed: int = 5,
-                     tf_pool: int = 0):
+                     tf_pool: int = 0, window=None):
     """A Poisson stream of TF-change requests: exponential inter-arrival gaps
     of mean 1/rate_hz over [0, seconds), each with a uniformly random volume id
     and a random trapezoid TF of U{ramps} ramps.  With `tf_pool` > 0 each
     volume draws its TFs from a pool of that many (the arrays are shared, so
-    long high-rate streams stay small in host memory).  Returns a list of
-    (arrival seconds, volume id, opacity table)."""
+    long high-rate streams stay small in host memory).  With window=(size,
+    period_s) the id is drawn from `size` consecutive entries of vol_ids
+    (wrapping around) that start at entry floor(t / period_s): the working
+    set drifts by one volume per period, so a catalog larger than the
+    server's slots sees a new volume, and an eviction, every period.
+    Returns a list of (arrival seconds, volume id, opacity table)."""
     rng = np.random.default_rng(seed)
     vol_ids = list(vol_ids)
     pools = {}
@@ -391,7 +395,11 @@ def poisson_requests(rate_hz: float, seconds: float, vol_ids, levels_of, ramps=(
         t += rng.exponential(1.0 / rate_hz)
         if t >= seconds:
             break
-        v = vol_ids[int(rng.integers(0, len(vol_ids)))]
+        if window is None:
+            v = vol_ids[int(rng.integers(0, len(vol_ids)))]
+        else:
+            size, period = window
+            v = vol_ids[(int(t // period) + int(rng.integers(0, size))) % len(vol_ids)]
         if tf_pool > 0:
             alpha = pools[v][int(rng.integers(0, tf_pool))]
         else:
