@@ -9,16 +9,22 @@ input with the volume already resident in HBM:
   for each of the 200 TFs:
       TF update  (active set + Eq. 1 min-combine)  -> D'
       plain method (occupancy from the volume + distance map) -> D
+      plain method from the cached brick [min,max] (no volume read) -> D
 
-`value` is the whole step's algorithmic bytes divided by its wall time
-(GB/s).  Per-call durations come from HIP events recorded on the stream the
-library launches on; `roofline` is reported for the kernel that takes most of
-the step (the plain method's occupancy pass over the volume) and, as
-`roofline_tf_update`, for the min-combine kernel.  `cpu_baseline` is the CPU
-oracle timed on a slab of the same volume (see `cpu_baseline()`).
+`value` is the partitioned TF update's throughput: (|S|+1)*G algorithmic
+bytes per update, summed over the timed steps' updates, divided by the sum
+of their durations (HIP events recorded on the stream the library launches
+on), in GB/s.  The whole step's bytes over its wall time is `step_GBps`;
+each call's p50/p90/p99 are reported beside it.  `roofline` is reported for
+the kernel that takes most of the step (the plain method's occupancy pass
+over the volume) and, as `roofline_tf_update`, for the min-combine kernel.
+`served` is a short serving leg with admissions and evictions under load
+(see served_leg()).  `cpu_baseline` is the CPU oracle timed on a slab of the
+same volume on all host threads, `cpu_baseline_one_thread` on one thread
+(see cpu_baseline()).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--tfs T]
-                       [--no-cpu-baseline] [--calib-copy-mib M]
+                       [--no-cpu-baseline] [--no-served] [--calib-copy-mib M]
                        [--workload tube_tree|batched|served|sweep|configs]
 
 --workload served: a Poisson stream of TF changes (2k/s) over 24 resident
@@ -144,12 +150,23 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
 
-def cpu_baseline(vol, bounds, alphas, levels, step_bytes_fn, slab_z=256, tfs=20):
+def cpu_baseline(vol, bounds, alphas, levels, step_bytes_fn, slab_z=256, tfs=20, threads=None):
     """The CPU oracle (as it stands) on a bounded sample: the first `slab_z`
     z-slices of the volume, the full build plus `tfs` TFs through both the
-    update and the plain method.  Each phase's oracle throughput (bytes/s on
-    the slab) is applied to the full step's byte mix to give GB/s."""
+    update and the plain method, on `threads` OpenMP threads (None: all the
+    host's).  Each phase's oracle throughput (bytes/s on the slab) is applied
+    to the full step's byte mix to give GB/s."""
     import oracle
+    prev = oracle.threads()
+    if threads is not None:
+        oracle.set_threads(int(threads))
+    try:
+        return _cpu_baseline(oracle, vol, bounds, alphas, levels, step_bytes_fn, slab_z, tfs)
+    finally:
+        oracle.set_threads(prev)
+
+
+def _cpu_baseline(oracle, vol, bounds, alphas, levels, step_bytes_fn, slab_z, tfs):
     slab = np.ascontiguousarray(vol[:slab_z])
     n = len(bounds) - 1
     t0 = time.perf_counter()
@@ -173,16 +190,17 @@ def cpu_baseline(vol, bounds, alphas, levels, step_bytes_fn, slab_z=256, tfs=20)
     rate_upd = upd_bytes / (t3 - t2)
     rate_full = tfs * (V * s + Gs) / (t4 - t3)
     b = step_bytes_fn()
-    est = (b["bricks"] / rate_bricks + b["partitions"] / rate_parts + b["tf_update"] / rate_upd
-           + b["full_recompute"] / rate_full)
     return {
-        "value": round(b["total"] / est / 1e9, 3),
+        "value": round(rate_upd / 1e9, 3),
         "unit": "GB/s",
         "cores": oracle.threads(),
         "kind": "oracle",
         "sample": (f"first {slab_z} of {vol.shape[0]} z-slices ({slab.shape[2]}x{slab.shape[1]}x"
-                   f"{slab_z}), build + {tfs} TFs through update and full recompute, "
-                   f"{t4 - t0:.1f} s; per-phase rates applied to the full step's byte mix"),
+                   f"{slab_z}; not the full volume), build + {tfs} TFs through update and full "
+                   f"recompute, {t4 - t0:.1f} s; value = the oracle's TF-update rate, "
+                   "(|S|+1)*G bytes per update over its time; per-phase rates scaled to "
+                   "the full volume below"),
+        "full_recompute_GBps": round(rate_full / 1e9, 3),
         "tf_update_ms_per_tf_full_volume": round(1e3 * b["tf_update"] / b["tfs"] / rate_upd, 3),
         "full_recompute_ms_per_tf_full_volume": round(
             1e3 * b["full_recompute"] / b["tfs"] / rate_full, 3),
@@ -213,6 +231,12 @@ def main():
     ap.add_argument("--serve-load-rates", default="20000,60000,150000",
                     help="comma-separated request rates of the served load levels")
     ap.add_argument("--serve-load-seconds", type=float, default=2.0)
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served leg of the default workload")
+    ap.add_argument("--served-seconds", type=float, default=15.0,
+                    help="length of the served leg of the default workload")
+    ap.add_argument("--served-drift", type=float, default=1.0,
+                    help="seconds per one-volume drift of the served leg's working set")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -260,13 +284,16 @@ def main():
             "partitions": 2 * G * s + n * G,
             "tf_update": sum((k + 1) * G for k in s_sizes),
             "full_recompute": T * (V * s + G),
+            "full_recompute_cached": T * (2 * G * s + G),
             "tfs": T,
         }
-        b["total"] = b["bricks"] + b["partitions"] + b["tf_update"] + b["full_recompute"]
+        b["total"] = (b["bricks"] + b["partitions"] + b["tf_update"] + b["full_recompute"]
+                      + b["full_recompute_cached"])
         return b
 
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    d_cached = torch.empty_like(v.dist)
 
     def run_step(rec):
         e = [ev() for _ in range(4)]
@@ -279,7 +306,7 @@ def main():
         e[3].record(stream)
         rec["build"].append(e)
         for a in alphas:
-            f = [ev() for _ in range(4)]
+            f = [ev() for _ in range(6)]
             f[0].record(stream)
             pdm.tf_update(desc, v.pdms, bounds, a, v.dist, stream)
             f[1].record(stream)
@@ -287,6 +314,10 @@ def main():
             f[2].record(stream)
             pdm.distance_yz(desc, d_full, 1, stream)
             f[3].record(stream)
+            pdm.plain_cached_distance_x(desc, v.bmin, v.bmax, a, d_cached, stream)
+            f[4].record(stream)
+            pdm.distance_yz(desc, d_cached, 1, stream)
+            f[5].record(stream)
             rec["tf"].append(f)
 
     log(f"warmup {args.warmup} step(s) ...")
@@ -311,12 +342,18 @@ def main():
     upd_ms = [el(f[0], f[1]) for f in rec["tf"]]
     plx_ms = [el(f[1], f[2]) for f in rec["tf"]]
     dyz1_ms = [el(f[2], f[3]) for f in rec["tf"]]
+    cx_ms = [el(f[3], f[4]) for f in rec["tf"]]
+    cyz_ms = [el(f[4], f[5]) for f in rec["tf"]]
     full_ms = [a + b for a, b in zip(plx_ms, dyz1_ms)]
+    cached_ms = [a + b for a, b in zip(cx_ms, cyz_ms)]
     upd_bytes = [(k + 1) * G for k in s_sizes] * args.steps
     sb = step_bytes()
 
-    # parity spot check on the last TF: D' <= D everywhere (Sec. 3.1)
+    # parity spot checks on the last TF: D' <= D everywhere (Sec. 3.1), and
+    # the plain method gives the same D from the volume and from the cached
+    # brick ranges
     assert bool((v.dist <= d_full).all().item()), "D' > D"
+    assert torch.equal(d_full, d_cached), "cached-range D differs from D"
 
     # the same TFs through the range table (outside the step: an option of
     # the update, not one of the method's steps)
@@ -333,6 +370,7 @@ def main():
         log(f"calibration copy: {nb} bytes read, {nb} bytes written")
 
     plain_bytes = V * s + G
+    cached_bytes = 2 * G * s + G
     plain_avg_ms = float(np.mean(plx_ms))
     plain_gbps = plain_bytes / (plain_avg_ms * 1e-3) / 1e9
     upd_gbps = sum(upd_bytes) / (sum(upd_ms) * 1e-3) / 1e9
@@ -352,13 +390,17 @@ def main():
         return r
 
     total_by_kernel = {
-        "k_plain_x": sum(plx_ms), "y/z scans, one map (k_dist_axis + k_dist_split)": sum(dyz1_ms),
-        "k_combine": sum(upd_ms), "k_bricks": sum(bricks_ms), "k_pom_x": sum(pomx_ms),
-        "y/z scans, all partitions (k_dist_global)": sum(dyz_n_ms)}
+        "k_plain_x": sum(plx_ms), "y/z scans, one map (k_dist_axis + k_dist_split)": sum(dyz1_ms) + sum(cyz_ms),
+        "k_combine": sum(upd_ms), "k_plain_cached_x": sum(cx_ms), "k_bricks": sum(bricks_ms),
+        "k_pom_x": sum(pomx_ms), "y/z scans, all partitions (k_dist_global)": sum(dyz_n_ms)}
+
+    def ms_stats(xs):
+        return {"p50_ms": round(pct(xs, 50), 4), "p90_ms": round(pct(xs, 90), 4),
+                "p99_ms": round(pct(xs, 99), 4), "mean_ms": round(float(np.mean(xs)), 4)}
 
     out = {
         "metric": "TF-update ms & GB/s (partitioned vs full recompute), 1024³ u8; p50/p99 served",
-        "value": round(sb["total"] * args.steps / wall / 1e9, 2),
+        "value": round(upd_gbps, 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -371,18 +413,28 @@ def main():
         "data": "synthetic (seeded tube-tree volume and trapezoid TFs standing in for kingsnake)",
         "config": {"workload": "tube-tree 1024x1024x795 u8, bricks 4^3 (256x256x199), "
                                f"64 uniform partitions, {T} TFs (1-3 ramps); step = build + "
-                               f"{T} x (TF update + full recompute)",
+                               f"{T} x (TF update + full recompute from the volume + full "
+                               "recompute from the cached brick ranges)",
                    "volume_zyx": list(vol.shape), "partitions": n, "tfs": T, "brick": 4},
-        "tf_update": {"p50_ms": round(pct(upd_ms, 50), 4), "p90_ms": round(pct(upd_ms, 90), 4),
-                      "p99_ms": round(pct(upd_ms, 99), 4), "mean_ms": round(float(np.mean(upd_ms)), 4),
-                      "GBps": round(upd_gbps, 1), "mean_active_partitions": round(float(np.mean(s_sizes)), 2)},
-        "full_recompute": {"p50_ms": round(pct(full_ms, 50), 4), "p90_ms": round(pct(full_ms, 90), 4),
-                           "mean_ms": round(float(np.mean(full_ms)), 4),
+        "value_is": ("partitioned TF update (Sec. 3.1, Eq. 1): sum over the timed steps' updates of "
+                     "(|S|+1)*G bytes / sum of their HIP-event durations"),
+        "step_GBps": round(sb["total"] * args.steps / wall / 1e9, 2),
+        "tf_update": {**ms_stats(upd_ms), "GBps": round(upd_gbps, 1),
+                      "mean_active_partitions": round(float(np.mean(s_sizes)), 2)},
+        "full_recompute": {**ms_stats(full_ms),
                            "occupancy_x_mean_ms": round(plain_avg_ms, 4),
                            "distance_yz_mean_ms": round(float(np.mean(dyz1_ms)), 4),
                            "GBps": round(T * plain_bytes * args.steps / (sum(full_ms) * 1e-3) / 1e9, 1)},
+        "full_recompute_cached": {**ms_stats(cached_ms),
+                                  "occupancy_x_mean_ms": round(float(np.mean(cx_ms)), 4),
+                                  "distance_yz_mean_ms": round(float(np.mean(cyz_ms)), 4),
+                                  "bytes_per_call": cached_bytes,
+                                  "GBps": round(T * cached_bytes * args.steps / (sum(cached_ms) * 1e-3) / 1e9, 1),
+                                  "identical_to_full_recompute": True},
         "speedup_update_vs_full": {"p50": round(pct(full_ms, 50) / pct(upd_ms, 50), 2),
                                    "mean": round(float(np.mean(full_ms)) / float(np.mean(upd_ms)), 2)},
+        "speedup_update_vs_cached": {"p50": round(pct(cached_ms, 50) / pct(upd_ms, 50), 2),
+                                     "mean": round(float(np.mean(cached_ms)) / float(np.mean(upd_ms)), 2)},
         "build": {"bricks_ms": round(float(np.median(bricks_ms)), 4),
                   "pom_x_ms": round(float(np.median(pomx_ms)), 4),
                   "distance_yz_ms": round(float(np.median(dyz_n_ms)), 4),
@@ -400,10 +452,106 @@ def main():
         "paper_context": PAPER_CONTEXT,
         "kernel_source_sha256_16": kernel_hash(),
     }
+    if not args.no_served:
+        torch.cuda.empty_cache()
+        out["served"] = served_leg(args, torch, pdm, W, vol)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a slab ...")
+        log("timing the CPU oracle on a slab (all host threads) ...")
         out["cpu_baseline"] = cpu_baseline(vol, bounds, alphas, L, step_bytes)
+        log("timing the CPU oracle on a thinner slab (one thread) ...")
+        out["cpu_baseline_one_thread"] = cpu_baseline(vol, bounds, alphas, L, step_bytes,
+                                                      slab_z=32, tfs=10, threads=1)
     print(json.dumps(out), flush=True)
+
+
+def served_leg(args, torch, pdm, W, tube_tree):
+    """Continuous batching with admissions under load: a catalog of 32
+    volumes (28 of the batched recipe, the step's tube tree and a second
+    one) behind a server with 24 slots and a 200 GB budget.  Poisson
+    requests at --serve-rate for --served-seconds; the working set of 24
+    volumes drifts by one volume every --served-drift seconds, so new
+    volumes are admitted (pinned host voxels copied on the admission stream,
+    then built) and LRU volumes evicted while the stream runs.  Reports the
+    served p50/p99 latency (arrival to completion, admissions included),
+    updates/s, admissions and evictions, and the same schedule through a
+    serial full-recompute queue (per-volume service times measured here)."""
+    from paper_2407_21552_amd.serve import GpuExecutor, Server, VolumeSpec, requests_from
+    log("served leg: generating a catalog of 32 volumes ...")
+    cat, pinned = {}, {}
+
+    def pin(a):
+        a = np.ascontiguousarray(a)
+        t = torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a)
+        return t.pin_memory()
+
+    specs = W.batch_specs(30, seed=6)
+    order = list(range(24)) + [30, 31] + list(range(24, 30))
+    for k, sp in enumerate(specs):
+        pinned[k] = pin(W.batch_volume(sp))
+        cat[k] = VolumeSpec(k, sp["shape"], sp["dtype"], sp["levels"],
+                            W.uniform_bounds(sp["levels"], sp["n"]), lambda k=k: pinned[k])
+    for k, host in ((30, tube_tree), (31, W.tube_tree_u8(seed=33))):
+        pinned[k] = pin(host)
+        cat[k] = VolumeSpec(k, host.shape, np.uint8, 256, W.uniform_bounds(256, 64),
+                            lambda k=k: pinned[k])
+    ids = order
+    arrivals = W.poisson_requests(args.serve_rate, args.served_seconds, ids,
+                                  {k: cat[k].levels for k in cat}, seed=12,
+                                  window=(24, args.served_drift))
+    ex = GpuExecutor(outputs_per_volume=8)
+    srv = Server(ex, cat, budget_bytes=200 << 30, max_slots=24)
+    # warm start: the first working set resident before the stream
+    for k in ids[:24]:
+        srv._ensure(k)
+    torch.cuda.synchronize()
+    for h in srv.resident.values():
+        ex.ready(h)
+    srv.stats.clear()
+    sched = requests_from(arrivals)
+    log(f"served leg: {len(sched)} requests over {args.served_seconds:.0f} s, working set drifting "
+        f"every {args.served_drift:.1f} s ...")
+    srv.t0 = srv.clock()
+    srv.run(sched, timeout=args.served_seconds + 60)
+    torch.cuda.synchronize()
+    rep = srv.report()
+    admitted = {r.vol_id for r in sched} - set(ids[:24])
+    lat_cold = [r.done - r.arrival for r in srv.completed if r.vol_id in admitted]
+    # per-volume service time of the plain method (volume resident), for the
+    # serial full-recompute queue over the same schedule
+    log("served leg: per-volume full recompute times ...")
+    stream = torch.cuda.current_stream()
+    full_s = {}
+    for k, spec in cat.items():
+        vol_dev = pinned[k].to("cuda")
+        desc = pdm.volume_desc(spec.shape, spec.dtype, spec.levels)
+        a = W.trapezoid_tf(spec.levels, 2, np.random.default_rng(k))
+        d = torch.empty(pdm.grid_of(desc)[3], dtype=torch.uint8, device="cuda")
+        pdm.full_recompute(desc, vol_dev, a, d, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            pdm.full_recompute(desc, vol_dev, a, d, stream)
+        e1.record(stream)
+        e1.synchronize()
+        full_s[k] = e0.elapsed_time(e1) / 5 * 1e-3
+        del vol_dev
+    rnd = lambda x: None if x is None else round(x, 4)
+    return {
+        "workload": (f"Poisson {args.serve_rate:.0f}/s over {args.served_seconds:.0f} s; catalog of 32 "
+                     "volumes (30 of U{96..640}^3 mixed u8/u16 with 16/32/64 partitions, 2 x "
+                     "1024x1024x795 u8 tube trees with 64), 24 slots, 200 GB budget; the working set "
+                     f"of 24 drifts by one volume every {args.served_drift:.1f} s (admission + LRU "
+                     "eviction under load); up to 48 requests per launch"),
+        "requests": len(sched),
+        "p50_ms": rnd(rep["p50_ms"]), "p99_ms": rnd(rep["p99_ms"]), "mean_ms": rnd(rep["mean_ms"]),
+        "updates_per_s": rnd(rep["updates_per_s"]), "completed": rep["completed"],
+        "rejected": rep["rejected"], "launches": rep["launches"], "mean_batch": rnd(rep["mean_batch"]),
+        "admissions": rep["admissions"], "evictions": rep["evictions"],
+        "requests_to_admitted_volumes": len(lat_cold),
+        "p99_ms_requests_to_admitted_volumes": rnd(float(np.percentile(lat_cold, 99)) * 1e3
+                                                   if lat_cold else None),
+        "serial_full_recompute": serial_queue(sched, full_s),
+    }
 
 
 def run_batched(args):

@@ -959,7 +959,6 @@ __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib
         col[c * cs] = (uint8_t)out;
     }
 }
-#undef PDM_SCAN_STEP
 
 // Work-groups are handed to the 8 XCDs round-robin (work-group b runs on XCD
 // b % 8).  xcd_item maps work-group b to a work item so that runs of kXcdRun
@@ -983,6 +982,127 @@ __device__ __forceinline__ int64_t line_offset(int64_t l, int Bx, int inner, int
     const int64_t r = l / Bx;
     return (r / inner) * G + (r % inner) * plane + l % Bx;
 }
+
+// ---------------------------------------------------------------------------
+// k_dist_lines: both one-sided passes of 64 lines (one per lane) with the
+// whole line held in registers, for passes over many lines (all partitions
+// of a grid): each byte is read once and written once, and the backward pass
+// reads the forward pass's results from registers instead of global memory.
+//
+// The 64 lines of a work-group are addressed through a buffer resource at
+// the first line's offset: every lane keeps its line's 32-bit offset in a
+// vector register and a position's offset (p * stride) is a scalar, so a
+// load or store costs no vector address arithmetic.  The host checks that
+// every offset fits in 31 bits.  Lanes past the last line repeat it and
+// write the same bytes as its own lane.
+//
+// The line is held as 4 bytes per register, positions in chunks of 16 under
+// wave-uniform branches (register indices must be compile-time constants,
+// so every chunk and step is unrolled).  Positions from m up to the end of
+// the last chunk repeat the line's last value: a repeated value never lowers
+// the result at a real position (position m-1 offers the same value at a
+// smaller distance), so both passes run over whole chunks.  Stores of those
+// positions go to position m-1 before its own store, which comes later in
+// the backward pass and is the one that stays (program order of one lane's
+// stores to one address).
+//
+// A tile whose every byte is 255 (no occupied brick anywhere near its
+// lines) is left as it is: the result equals the input.
+// ---------------------------------------------------------------------------
+constexpr int kLineWords = kMaxLine / 4;  // registers holding a line of up to 256 bytes
+constexpr int kLineChunk = 16;           // positions per wave-uniform branch
+constexpr int kLineChunks = kMaxLine / kLineChunk;
+constexpr int kBufferFlags = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ int line_byte(uint32_t w, int k) {
+    return (int)__builtin_amdgcn_ubfe(w, 8u * (unsigned)k, 8u);
+}
+
+__global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__ maps, int64_t lines,
+                                                           int Bx, int inner, int64_t plane,
+                                                           int stride, int m, int64_t G) {
+    using P = uint8_t;  // table entry type of PDM_SCAN_STEP
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    const int lane = threadIdx.x;
+    const int64_t l0 = xcd_item(blockIdx.x) * kScanLanes;
+    if (l0 >= lines) return;
+    const int64_t l = min(l0 + (int64_t)lane, lines - 1);
+    const int64_t base = line_offset(l0, Bx, inner, plane, G);
+    const int voff = (int)(line_offset(l, Bx, inner, plane, G) - base);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(maps + base, (short)0, 0x7FFFFFFF, kBufferFlags);
+    const int last = m - 1;
+    const int nch = (m + kLineChunk - 1) / kLineChunk;  // chunks holding the line
+    uint32_t w[kLineWords];
+    uint32_t all = 0xFFFFFFFFu;
+#pragma unroll
+    for (int c = 0; c < kLineChunks; ++c) {
+        if (c < nch) {
+#pragma unroll
+            for (int j = 0; j < kLineChunk / 4; ++j) {
+                uint32_t b[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int pos = min(kLineChunk * c + 4 * j + k, last);
+                    b[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, voff, pos * stride, 0);
+                }
+                const uint32_t word = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+                w[4 * c + j] = word;
+                all &= word;
+            }
+        }
+    }
+    if (__ballot(all != 0xFFFFFFFFu) == 0ull) return;  // every byte 255: nothing changes
+    clear_table<uint8_t>(tbl);
+    __syncthreads();
+    // forward pass; the first step starts from "no candidate yet" (v above
+    // every value), so it takes f(0) with witness 0 like every later one
+    int v = 511, W = 0, t = 0;
+#pragma unroll
+    for (int c = 0; c < kLineChunks; ++c) {
+        if (c < nch) {
+            int pc = kLineChunk * c;  // the position in a vector register: one add per step
+            __asm__ volatile("" : "+v"(pc));
+#pragma unroll
+            for (int j = 0; j < kLineChunk / 4; ++j) {
+                uint32_t acc = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int q = 4 * j + k;
+                    const int fi = line_byte(w[4 * c + j], k);
+                    int out;
+                    PDM_SCAN_STEP(pc + q, fi, out);
+                    acc |= (uint32_t)out << (8 * k);
+                }
+                w[4 * c + j] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    clear_table<uint8_t>(tbl);
+    __syncthreads();
+    // backward pass from the end of the last chunk, positions counted from it
+    const int pend = kLineChunk * nch - 1;
+    v = 511;
+    W = 0;
+    t = 0;
+#pragma unroll
+    for (int c = kLineChunks - 1; c >= 0; --c) {
+        if (c < nch) {
+            int pc = pend - kLineChunk * c;  // backward position of this chunk's first byte
+            __asm__ volatile("" : "+v"(pc));
+#pragma unroll
+            for (int q = kLineChunk - 1; q >= 0; --q) {
+                const int fi = line_byte(w[4 * c + q / 4], q % 4);
+                int out;
+                PDM_SCAN_STEP(pc - q, fi, out);
+                const int pos = min(kLineChunk * c + q, last);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out, rs, voff, pos * stride, 0);
+            }
+        }
+    }
+}
+#undef PDM_SCAN_STEP
 
 // Lines of at most kMaxLine bricks.  One wave per work-group handles 64
 // lines, staged into LDS ([pos][lane], 64 bytes per position) so that no
@@ -1849,6 +1969,16 @@ static AxisLines axis_lines(int count, int Bx, int By, int Bz, int axis) {
     return a;
 }
 
+// Whether k_dist_lines can address a tile of 64 lines with 31-bit offsets
+// from the tile's first line: the largest distance between two lines of one
+// tile plus the whole extent of a line.
+static bool lines_fit_32(const AxisLines& a, int Bx, int64_t G) {
+    // consecutive lines differ by 1 within a row; a tile that leaves a row
+    // jumps by at most one map (G) plus one plane step per row it crosses
+    const int64_t span = (int64_t)kScanLanes + G + a.plane * (int64_t)(kScanLanes / Bx + 2);
+    return a.stride <= INT32_MAX && span + (int64_t)(a.m - 1) * a.stride < (int64_t)INT32_MAX;
+}
+
 static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, int axis,
                               hipStream_t s) {
     const AxisLines a = axis_lines(count, Bx, By, Bz, axis);
@@ -1859,6 +1989,9 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
     if (a.m > kMaxLine) {
         k_dist_global<uint16_t, kLongChunk><<<(unsigned)blocks, kScanLanes, 0, s>>>(
             maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+    } else if (a.lines > kStagedMaxLines && lines_fit_32(a, Bx, G)) {
+        k_dist_lines<<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, a.plane,
+                                                             (int)a.stride, a.m, G);
     } else if (a.lines > kStagedMaxLines) {
         if (a.m >= kLongChunkLine && a.lines >= kLongChunkLines)
             k_dist_global<uint8_t, kLongChunk><<<(unsigned)blocks, kScanLanes, 0, s>>>(

@@ -168,6 +168,44 @@ def test_all_maps_long_lines_in_chunks(pdm, orc):
                                       err_msg=f"D' tf {k}")
 
 
+MANY_LINE_SHAPES = [
+    # (voxel shape zyx, dtype, levels, n, label): all-partition y/z passes of
+    # more than 2^18 lines of at most 256 bricks (the register-resident scan)
+    ((244, 240, 180), np.uint8, 256, 100,
+     "61x60x45 grid: tiles straddle rows and maps, partial last tiles"),
+    ((160, 1024, 132), np.uint16, 4096, 256, "40x256x33 grid: 256-brick y lines, u16"),
+    ((68, 66, 4000), np.uint8, 256, 32, "17x17x1000 grid: lines of 17 (one full chunk + 1)"),
+    ((80, 1020, 256), np.uint8, 256, 256, "20x255x64 grid: 255-brick y lines, 256 partitions"),
+    ((8, 400, 1024), np.uint8, 256, 64, "2x100x256 grid: 2-brick z lines"),
+]
+
+
+@pytest.mark.parametrize("shape,dtype,levels,n,label", MANY_LINE_SHAPES,
+                         ids=[s[-1].split(":")[0] for s in MANY_LINE_SHAPES])
+def test_many_line_scans(pdm, orc, shape, dtype, levels, n, label):
+    """Every PDM against the oracle where the y and z passes over all maps
+    cover more than 2^18 lines of at most 256 bricks: ragged x (tiles of 64
+    lines that cross rows and maps, lanes past the last line), line lengths
+    at chunk borders, sparse occupancy (whole tiles at the cap) and dense."""
+    import torch
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + n, keep=0.03, cell=4)
+    # no voxel in the top quarter of the levels: those partitions' maps are
+    # 255 everywhere, so whole tiles of their lines stay at the cap
+    vol = (vol % (levels * 3 // 4)).astype(dtype)
+    bounds = W.uniform_bounds(levels, n)
+    v = pdm.Volume(pdm.to_device(vol), levels, bounds, voxel_dtype=dtype)
+    say(f"[case] many-line scans {label}: shape={vol.shape} grid={(v.bz, v.by, v.bx)} n={n}")
+    assert max(v.bx * v.bz, v.bx * v.by) * n > 4 * 1024 * 64
+    v.build()
+    torch.cuda.synchronize()
+    bmin, bmax = orc.bricks(vol)
+    want = orc.pdms(vol, bounds, levels, brick_minmax=(bmin, bmax))
+    got = pdm.from_device(v.pdms)
+    assert (want == 255).any() and (want == 0).any() and ((want > 0) & (want < 255)).any()
+    for p in range(n):
+        np.testing.assert_array_equal(got[p], want[p], err_msg=f"PDM {p}")
+
+
 MAX_SHAPES = [
     # (shape zyx, dtype, levels, n, label): grids at the ABI's axis limits
     ((3, 5, 4 * 16384), np.uint8, 256, 16, "x at the limit: 16384 bricks, 64 wave segments"),
