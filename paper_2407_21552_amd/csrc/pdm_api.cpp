@@ -583,6 +583,8 @@ pdm_status pdm_plain_cached_distance_x(const pdm_volume* v, const void* d_bmin, 
     a.nwords = pa.nwords;
     a.levels = pa.levels;
     a.store_vec = pa.store_vec;
+    a.load_vec = pa.Bx % 4 == 0 && aligned(d_bmin, 4 * (uintptr_t)v->dtype) &&
+                 aligned(d_bmax, 4 * (uintptr_t)v->dtype);
     return from_hip(pdm::launch_plain_cached_x(a, bits, stream));
 }
 

@@ -575,16 +575,50 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
 
 // ---------------------------------------------------------------------------
 // Plain method from the cached brick [min,max] (the volume is not read): the
-// same occupancy test as k_plain_x on bmin/bmax, then the x distances.  The
-// row layout follows k_pom_x: rows of at most 128 bricks packed 64/W to a
-// wave, one wave per row up to 256 bricks, 256-brick segments beyond.
+// same occupancy test as k_plain_x on bmin/bmax, then the x distances.
+// Rows of up to 256 bricks: W lanes per row (the power of two with 4W >= Bx),
+// so one wave pass covers 64/W rows, and a wave takes kCachedPasses passes
+// with the loads of all of them issued first (4 bricks per lane, one vector
+// load each for bmin and bmax when rows and pointers allow).  Longer rows:
+// one wave per row in 256-brick segments.
 // ---------------------------------------------------------------------------
+constexpr int kCachedPasses = 4;
+
+template <typename T>
+struct Quad {
+    T v[4];
+};
+
+// Bricks x0 .. x0+3 of a row (nb of them inside it; the rest get `fill`).
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(const T* __restrict__ p, int64_t idx, int nb, bool vec,
+                                             T fill) {
+    Quad<T> q;
+    if (vec && nb == 4) {
+        if constexpr (sizeof(T) == 1) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(p + idx);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q.v[k] = (T)(w >> (8 * k));
+        } else {
+            const uint2 w = *reinterpret_cast<const uint2*>(p + idx);
+            q.v[0] = (T)w.x;
+            q.v[1] = (T)(w.x >> 16);
+            q.v[2] = (T)w.y;
+            q.v[3] = (T)(w.y >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q.v[k] = k < nb ? p[idx + k] : fill;
+    }
+    return q;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_plain_cached_x(const T* __restrict__ bmin,
                                                         const T* __restrict__ bmax, int Bx,
                                                         int64_t rows, AlphaBits bits, int nwords,
                                                         int levels, uint8_t* __restrict__ dist,
-                                                        int store_vec, int W) {
+                                                        int store_vec, int W, int load_vec) {
     __shared__ uint32_t s_words[PDM_ALPHA_WORDS];
     __shared__ uint16_t s_pre[PDM_ALPHA_WORDS + 1];
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
@@ -592,35 +626,47 @@ __global__ void __launch_bounds__(256) k_plain_cached_x(const T* __restrict__ bm
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t top = (uint32_t)levels - 1u;
-    // occupancy nibble of bricks x0 .. x0+3 of the row starting at rbase
-    auto nibble = [&](int64_t rbase, int x0, int nb) -> uint32_t {
+    auto nibble = [&](const Quad<T>& a, const Quad<T>& b, int nb) -> uint32_t {
         uint32_t o = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (k < nb && any_bit(s_words, s_pre, umin((uint32_t)bmin[rbase + x0 + k], top),
-                                  umin((uint32_t)bmax[rbase + x0 + k], top)))
+            if (k < nb && any_bit(s_words, s_pre, umin((uint32_t)a.v[k], top), umin((uint32_t)b.v[k], top)))
                 o |= 1u << k;
         return o;
     };
-    if (W < kWave) {
-        const int per = kWave / W;
-        const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave)) * per;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (W <= kWave && Bx <= kSegBricks) {
+        const int per = kWave / W;  // rows per wave pass
+        const int64_t row0 = wave * per * kCachedPasses;
         if (row0 >= rows) return;  // wave-uniform
-        const int64_t row = row0 + lane / W;
         const int q = lane & (W - 1);
-        const int nb = row < rows ? max(0, min(4, Bx - 4 * q)) : 0;
-        const int64_t rbase = row * Bx;
-        const uint32_t packed = x_distances_rows(nibble(rbase, 4 * q, nb), lane, W);
-        if (nb > 0) store_quad(dist, rbase + 4 * q, nb, packed, store_vec);
+        Quad<T> mn[kCachedPasses], mx[kCachedPasses];
+        int nb[kCachedPasses];
+#pragma unroll
+        for (int j = 0; j < kCachedPasses; ++j) {
+            const int64_t row = row0 + (int64_t)j * per + lane / W;
+            nb[j] = row < rows ? max(0, min(4, Bx - 4 * q)) : 0;
+            const int64_t idx = row * Bx + 4 * q;
+            mn[j] = load_quad<T>(bmin, idx, nb[j], load_vec, (T)0);
+            mx[j] = load_quad<T>(bmax, idx, nb[j], load_vec, (T)0);
+        }
+#pragma unroll
+        for (int j = 0; j < kCachedPasses; ++j) {
+            const int64_t row = row0 + (int64_t)j * per + lane / W;
+            const uint32_t packed = x_distances_rows(nibble(mn[j], mx[j], nb[j]), lane, W);
+            if (nb[j] > 0) store_quad(dist, row * Bx + 4 * q, nb[j], packed, store_vec);
+        }
         return;
     }
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int64_t row = wave;
     if (row >= rows) return;  // wave-uniform
     const int nseg = (Bx + kSegBricks - 1) / kSegBricks;
     const int64_t rbase = row * Bx;
     auto seg_nibble = [&](int seg) -> uint32_t {
         const int x = seg * kSegBricks + 4 * lane;
-        return nibble(rbase, x, max(0, min(4, Bx - x)));
+        const int nb = max(0, min(4, Bx - x));
+        return nibble(load_quad<T>(bmin, rbase + x, nb, false, (T)0),
+                      load_quad<T>(bmax, rbase + x, nb, false, (T)0), nb);
     };
     int prev_last = -kNone;
     uint32_t cur = seg_nibble(0);
@@ -830,17 +876,15 @@ constexpr int kMaxLine = 256;   // longest line staged in LDS
 // fill the chip's 1024 SIMDs with more than a few waves each, so per-wave
 // latency matters more than occupancy.
 constexpr int64_t kStagedMaxLines = 4 * 1024 * kScanLanes;
-// Steps per chunk of the global-memory scans (values loaded into registers
-// before their steps run).  Measured over all maps of a grid, 32 against 16:
-// 3% faster for 256x256x199 (64 maps: lines of 256 and 199 bricks, over 3M
-// lines per pass) and for 208-brick lines of 208x208x124; 5-10% slower for
-// 128- and 115-brick lines, for 256-brick lines when only 0.4M of them share
-// the pass, and for the batched scans (lines of 24 to 160 bricks).  Lines
-// shorter than a chunk run step by step.
+// Steps per chunk of the global-memory scans, which serve lines of more than
+// 256 bricks and passes whose offsets exceed the register kernels' 31 bits
+// (values loaded into registers before their steps run).  Measured over all
+// maps of a grid, 32 against 16: 3% faster for lines of 199 to 256 bricks
+// over more than 2^20 lines, 5-10% slower for shorter lines or fewer lines.
+// Lines shorter than a chunk run step by step.
 constexpr int kLongChunk = 32;
 constexpr int kLongChunkLine = 192;
 constexpr int64_t kLongChunkLines = 1 << 20;
-constexpr int kBatchChunk = 16;
 
 template <typename P>
 __device__ __forceinline__ void clear_table(P* tbl) {
@@ -1018,19 +1062,16 @@ __device__ __forceinline__ int line_byte(uint32_t w, int k) {
     return (int)__builtin_amdgcn_ubfe(w, 8u * (unsigned)k, 8u);
 }
 
-__global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__ maps, int64_t lines,
-                                                           int Bx, int inner, int64_t plane,
-                                                           int stride, int m, int64_t G) {
+// The two-sided pass of one line per lane, the line in registers: lane's
+// line at byte offsets voff + p * stride (p < m <= 256) from `base`, all
+// offsets below 2^31.  Called by the whole wave; returns early (all lanes)
+// when every byte of the wave's lines is 255.
+__device__ __forceinline__ void scan_lines_regs(uint8_t* base, int voff, int stride, int m,
+                                                uint8_t* __restrict__ tbl) {
     using P = uint8_t;  // table entry type of PDM_SCAN_STEP
-    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
-    const int lane = threadIdx.x;
-    const int64_t l0 = xcd_item(blockIdx.x) * kScanLanes;
-    if (l0 >= lines) return;
-    const int64_t l = min(l0 + (int64_t)lane, lines - 1);
-    const int64_t base = line_offset(l0, Bx, inner, plane, G);
-    const int voff = (int)(line_offset(l, Bx, inner, plane, G) - base);
+    const int lane = threadIdx.x & (kScanLanes - 1);
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(maps + base, (short)0, 0x7FFFFFFF, kBufferFlags);
+        __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7FFFFFFF, kBufferFlags);
     const int last = m - 1;
     const int nch = (m + kLineChunk - 1) / kLineChunk;  // chunks holding the line
     uint32_t w[kLineWords];
@@ -1038,13 +1079,17 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__
 #pragma unroll
     for (int c = 0; c < kLineChunks; ++c) {
         if (c < nch) {
+            // the chunk's scalar offsets are computed here, not all at once
+            // ahead of the loop (256 of them would spill)
+            int st = stride, lst = last;
+            __asm__ volatile("" : "+s"(st), "+s"(lst));
 #pragma unroll
             for (int j = 0; j < kLineChunk / 4; ++j) {
                 uint32_t b[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const int pos = min(kLineChunk * c + 4 * j + k, last);
-                    b[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, voff, pos * stride, 0);
+                    const int pos = min(kLineChunk * c + 4 * j + k, lst);
+                    b[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, voff, pos * st, 0);
                 }
                 const uint32_t word = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
                 w[4 * c + j] = word;
@@ -1054,7 +1099,7 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__
     }
     if (__ballot(all != 0xFFFFFFFFu) == 0ull) return;  // every byte 255: nothing changes
     clear_table<uint8_t>(tbl);
-    __syncthreads();
+    __syncthreads();  // work-groups of the callers are one wave
     // forward pass; the first step starts from "no candidate yet" (v above
     // every value), so it takes f(0) with witness 0 like every later one
     int v = 511, W = 0, t = 0;
@@ -1091,17 +1136,199 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__
         if (c < nch) {
             int pc = pend - kLineChunk * c;  // backward position of this chunk's first byte
             __asm__ volatile("" : "+v"(pc));
+            int st = stride, lst = last;
+            __asm__ volatile("" : "+s"(st), "+s"(lst));
 #pragma unroll
             for (int q = kLineChunk - 1; q >= 0; --q) {
                 const int fi = line_byte(w[4 * c + q / 4], q % 4);
                 int out;
                 PDM_SCAN_STEP(pc - q, fi, out);
-                const int pos = min(kLineChunk * c + q, last);
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out, rs, voff, pos * stride, 0);
+                const int pos = min(kLineChunk * c + q, lst);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)out, rs, voff, pos * st, 0);
             }
         }
     }
 }
+
+__global__ void __launch_bounds__(kScanLanes) k_dist_lines(uint8_t* __restrict__ maps, int64_t lines,
+                                                           int Bx, int inner, int64_t plane,
+                                                           int stride, int m, int64_t G) {
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    const int64_t l0 = xcd_item(blockIdx.x) * kScanLanes;
+    if (l0 >= lines) return;
+    const int64_t l = min(l0 + (int64_t)threadIdx.x, lines - 1);
+    const int64_t base = line_offset(l0, Bx, inner, plane, G);
+    const int voff = (int)(line_offset(l, Bx, inner, plane, G) - base);
+    scan_lines_regs(maps + base, voff, stride, m, tbl);
+}
+
+// ---------------------------------------------------------------------------
+// k_dist_pairs: the two-sided pass with two lanes per line, the line held in
+// registers, for passes over few lines (one map), where the chain of steps
+// of one wave sets the time.  Lanes L and L + 32 take line L of the
+// work-group's 32: the lower lane runs the forward one-sided pass and the
+// upper lane the backward one, each first over its half of the (padded)
+// line, then -- after the two lanes swap halves -- over the half the other
+// lane has finished.  A one-sided pass over the other direction's results
+// gives the two-sided result, so each lane ends holding the final values of
+// one half: half the chain of a one-lane pass, with no LDS tile.
+//
+// Both lanes of a pair run the same instructions on the same register
+// indices: the upper lane holds its line reversed (register r, byte k =
+// position pend - 4r - k, pend = 16*NCH - 1 the end of the padded line), so
+// step s of either lane is byte s%4 of register s/4.  NCH, the chunks of 16
+// positions the line spans, is a template argument because the swap
+// pairs registers r and 4*NCH-1-r.  Padding repeats the line's last value,
+// as in k_dist_lines.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t byte_reverse(uint32_t w) {
+    return __builtin_amdgcn_perm(w, w, 0x00010203u);
+}
+
+// Steps 4*R0 .. 4*R1-1 of one lane over registers R0 .. R1-1 of its line,
+// each output written over its input byte.  The step index lives in a
+// vector register, reset every 16 steps (one add per step).
+template <int R0, int R1, int NW>
+__device__ __forceinline__ void pairs_phase(uint32_t (&w)[NW], uint8_t* __restrict__ tbl, int lane,
+                                            int& v, int& W, int& t) {
+    using P = uint8_t;  // table entry type of PDM_SCAN_STEP
+    int pc = 0;
+    int pbase = 0;
+#pragma unroll
+    for (int r = R0; r < R1; ++r) {
+        if (r == R0 || r % 4 == 0) {
+            pbase = 4 * r;
+            pc = pbase;
+            __asm__ volatile("" : "+v"(pc));
+        }
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int out;
+            PDM_SCAN_STEP(pc + (4 * r - pbase) + k, line_byte(w[r], k), out);
+            acc |= (uint32_t)out << (8 * k);
+        }
+        w[r] = acc;
+    }
+}
+
+template <int NCH>
+__global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__ maps, int64_t lines,
+                                                           int Bx, int inner, int64_t plane,
+                                                           int stride, int m, int64_t G, int wide) {
+    constexpr int NW = 4 * NCH;          // registers per line
+    constexpr int H = 8 * NCH;           // steps per phase (half the padded line)
+    // the table; before and after the passes also the staging tile [pos][32]
+    __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
+    static_assert(32 * kMaxLine <= (int)sizeof(tbl), "the staging tile fits in the table's space");
+    const int lane = threadIdx.x;
+    const bool upper = lane >= 32;
+    const int li = lane & 31;
+    const int64_t l0 = xcd_item(blockIdx.x) * 32;
+    if (l0 >= lines) return;
+    const int64_t l = min(l0 + (int64_t)li, lines - 1);
+    const int64_t base = line_offset(l0, Bx, inner, plane, G);
+    const int voff = (int)(line_offset(l, Bx, inner, plane, G) - base);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(maps + base, (short)0, 0x7FFFFFFF, kBufferFlags);
+    const int last = m - 1;
+    uint32_t w[NW];
+    uint32_t all = 0xFFFFFFFFu;
+    if (wide) {
+        // the 32 lines are x0 .. x0+31 of one row and rows are 16-byte
+        // aligned: stage the tile with 16-byte pieces (two per position),
+        // then each lane gathers its column
+        const int q = lane & 1;
+        for (int r = lane >> 1; r < m; r += 32)
+            *reinterpret_cast<uint4*>(&tbl[r * 32 + 16 * q]) =
+                *reinterpret_cast<const uint4*>(maps + base + (int64_t)r * stride + 16 * q);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            uint32_t b[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = tbl[min(4 * r + k, last) * 32 + li];
+            w[r] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+            all &= w[r];
+        }
+        __syncthreads();  // the tile is read: its space becomes the table
+    } else {
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            uint32_t b[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                b[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, voff, min(4 * r + k, last) * stride, 0);
+            w[r] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+            all &= w[r];
+        }
+    }
+    if (__ballot(all != 0xFFFFFFFFu) == 0ull) return;  // every byte 255: nothing changes
+    // the upper lane's copy in backward order
+#pragma unroll
+    for (int j = 0; j < NW / 2; ++j) {
+        const uint32_t a = w[j], b = w[NW - 1 - j];
+        w[j] = upper ? byte_reverse(b) : a;
+        w[NW - 1 - j] = upper ? byte_reverse(a) : b;
+    }
+    clear_table<uint8_t>(tbl);
+    __syncthreads();
+    int v = 511, W = 0, t = 0;
+    // phase 1: steps 0 .. H-1 (registers 0 .. NW/2-1) over the lane's own half
+    pairs_phase<0, NW / 2>(w, tbl, lane, v, W, t);
+    // swap halves: register r (r >= NW/2) takes the other lane's register
+    // NW-1-r, reversed into this lane's order
+#pragma unroll
+    for (int r = NW / 2; r < NW; ++r)
+        w[r] = byte_reverse((uint32_t)__shfl_xor((int)w[NW - 1 - r], 32, kScanLanes));
+    // phase 2: steps H .. 2H-1 (registers NW/2 .. NW-1) over the other lane's results
+    pairs_phase<NW / 2, NW>(w, tbl, lane, v, W, t);
+    // the lower lane holds positions H .. pend in order; the upper lane
+    // positions 0 .. H-1 reversed, brought into order in registers 0 .. NW/2-1
+#pragma unroll
+    for (int j = 0; j < NW / 2; ++j) w[j] = byte_reverse(w[NW - 1 - j]);
+    if (wide) {
+        // back through the tile: each lane writes its half's column, then
+        // the rows leave in 16-byte pieces; the lower lane writes the padded
+        // positions to row m-1 before that row's own value
+        __syncthreads();  // every lane is done with the table
+        if (upper) {
+#pragma unroll
+            for (int r = 0; r < NW / 2; ++r)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) tbl[(4 * r + k) * 32 + li] = (uint8_t)(w[r] >> (8 * k));
+        } else {
+#pragma unroll
+            for (int r = NW - 1; r >= NW / 2; --r)
+#pragma unroll
+                for (int k = 3; k >= 0; --k)
+                    tbl[min(4 * r + k, last) * 32 + li] = (uint8_t)(w[r] >> (8 * k));
+        }
+        __syncthreads();
+        const int q = lane & 1;
+        for (int r = lane >> 1; r < m; r += 32)
+            *reinterpret_cast<uint4*>(maps + base + (int64_t)r * stride + 16 * q) =
+                *reinterpret_cast<const uint4*>(&tbl[r * 32 + 16 * q]);
+    } else if (upper) {
+        // positions 0 .. H-1: all inside the line (m > 16*(NCH-1) >= H for NCH >= 2)
+#pragma unroll
+        for (int r = 0; r < NW / 2; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(w[r] >> (8 * k)), rs, voff,
+                                                     (4 * r + k) * stride, 0);
+    } else {
+        // positions H .. pend, last first: stores of padded positions go to
+        // position m-1 before its own store
+#pragma unroll
+        for (int r = NW - 1; r >= NW / 2; --r)
+#pragma unroll
+            for (int k = 3; k >= 0; --k)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(w[r] >> (8 * k)), rs, voff,
+                                                     min(4 * r + k, last) * stride, 0);
+    }
+}
+
 #undef PDM_SCAN_STEP
 
 // Lines of at most kMaxLine bricks.  One wave per work-group handles 64
@@ -1649,33 +1876,22 @@ __device__ __forceinline__ void batch_scan_item(const BatchVol* __restrict__ vol
     const BatchVol& d = vols[batch_volume_of(vols, count, ph, t)];
     const int64_t local = t - d.first[ph];
     const int outer = (int)(local / d.chunks);  // z slice (phase 1) or y row (phase 2)
+    const int m = ph == 1 ? d.By : d.Bz;
+    if (m <= 1) return;  // a line of one brick is unchanged
+    const int stride = ph == 1 ? d.Bx : d.Bx * d.By;  // <= 2^16: axes of at most 256 bricks
+    const int64_t plane = ph == 1 ? (int64_t)outer * d.Bx * d.By : (int64_t)outer * d.Bx;
+    const int64_t nlines = (int64_t)d.n * d.Bx;
+    // offset of line (p, x) of this slice or row
+    auto offset = [&](int64_t line) { return (line / d.Bx) * d.G + plane + line % d.Bx; };
     for (int j = 0; j < lines_mult; ++j) {
-        // (p, x) lines of this slice or row, 64 per pass of the wave
-        const int64_t line = ((local % d.chunks) * lines_mult + j) * kWave + lane;
-        const bool active = line < (int64_t)d.n * d.Bx;
-        const int p = active ? (int)(line / d.Bx) : 0;
-        const int x = active ? (int)(line % d.Bx) : 0;
-        int64_t base, stride;
-        int m;
-        if (ph == 1) {
-            base = (int64_t)p * d.G + (int64_t)outer * d.Bx * d.By + x;
-            stride = d.Bx;
-            m = d.By;
-        } else {
-            base = (int64_t)p * d.G + (int64_t)outer * d.Bx + x;
-            stride = (int64_t)d.Bx * d.By;
-            m = d.Bz;
-        }
-        if (m > 1) {
-            PDM_GLB uint8_t* q = (PDM_GLB uint8_t*)d.pdms + (active ? base : 0);
-            clear_table<uint8_t>(tbl);
-            __builtin_amdgcn_wave_barrier();
-            one_sided_global<uint8_t, kBatchChunk>(q, stride, m, active, tbl);
-            __builtin_amdgcn_wave_barrier();
-            clear_table<uint8_t>(tbl);
-            __builtin_amdgcn_wave_barrier();
-            one_sided_global<uint8_t, kBatchChunk>(q + (int64_t)(m - 1) * stride, -stride, m, active, tbl);
-        }
+        // (p, x) lines of this slice or row, 64 per pass of the wave; lanes
+        // past the last line repeat it
+        const int64_t g0 = ((local % d.chunks) * lines_mult + j) * kWave;
+        if (g0 >= nlines) break;  // wave-uniform
+        const int64_t line = min(g0 + (int64_t)lane, nlines - 1);
+        const int64_t off0 = offset(g0);
+        // at most 64 lines apart: below 64 maps of at most 2^24 bricks
+        scan_lines_regs((uint8_t*)d.pdms + off0, (int)(offset(line) - off0), stride, m, tbl);
     }
 }
 
@@ -1884,16 +2100,19 @@ hipError_t launch_plain_cached_x(const CachedArgs& a, const AlphaBits& bits, hip
     const int64_t rows = (int64_t)a.By * a.Bz;
     int W = 1;  // lanes per row: the power of two with 4W >= Bx, at most a wave
     while (W < kWave && 4 * W < a.Bx) W *= 2;
-    const int64_t blocks = (rows + 4 * (kWave / W) - 1) / (4 * (kWave / W));
+    // rows per wave: kCachedPasses passes of 64/W rows up to 256 bricks, else one
+    const int64_t per_wave = a.Bx <= kSegBricks ? (int64_t)kCachedPasses * (kWave / W) : 1;
+    const int64_t waves = (rows + per_wave - 1) / per_wave;
+    const int64_t blocks = (waves + 3) / 4;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     if (a.bytes == 1)
         k_plain_cached_x<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(
             (const uint8_t*)a.bmin, (const uint8_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
-            a.dist, a.store_vec, W);
+            a.dist, a.store_vec, W, a.load_vec);
     else
         k_plain_cached_x<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(
             (const uint16_t*)a.bmin, (const uint16_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
-            a.dist, a.store_vec, W);
+            a.dist, a.store_vec, W, a.load_vec);
     return hipGetLastError();
 }
 
@@ -1989,6 +2208,28 @@ static hipError_t launch_axis(uint8_t* maps, int count, int Bx, int By, int Bz, 
     if (a.m > kMaxLine) {
         k_dist_global<uint16_t, kLongChunk><<<(unsigned)blocks, kScanLanes, 0, s>>>(
             maps, a.lines, Bx, a.inner, a.plane, a.stride, a.m, G);
+    } else if (a.lines <= kStagedMaxLines && a.m > kLineChunk && lines_fit_32(a, Bx, G)) {
+        const int64_t ptiles = (a.lines + 31) / 32;
+        const int64_t pblocks = (ptiles + kXcdSpan - 1) / kXcdSpan * kXcdSpan;
+        if (pblocks > INT32_MAX) return hipErrorInvalidValue;
+        const int nch = (a.m + kLineChunk - 1) / kLineChunk;
+        // 16-byte staging: groups of 32 lines never straddle a row, rows and
+        // the map base are 16-byte aligned
+        const int wide = Bx % 32 == 0 && a.stride % 16 == 0 && ((uintptr_t)maps & 15) == 0;
+        switch (nch) {
+#define PDM_PAIRS_CASE(N)                                                                    \
+    case N:                                                                                  \
+        k_dist_pairs<N><<<(unsigned)pblocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, \
+                                                                 a.plane, (int)a.stride, a.m, G, \
+                                                                 wide);                      \
+        break;
+            PDM_PAIRS_CASE(2) PDM_PAIRS_CASE(3) PDM_PAIRS_CASE(4) PDM_PAIRS_CASE(5)
+            PDM_PAIRS_CASE(6) PDM_PAIRS_CASE(7) PDM_PAIRS_CASE(8) PDM_PAIRS_CASE(9)
+            PDM_PAIRS_CASE(10) PDM_PAIRS_CASE(11) PDM_PAIRS_CASE(12) PDM_PAIRS_CASE(13)
+            PDM_PAIRS_CASE(14) PDM_PAIRS_CASE(15) PDM_PAIRS_CASE(16)
+#undef PDM_PAIRS_CASE
+            default: return hipErrorInvalidValue;
+        }
     } else if (a.lines > kStagedMaxLines && lines_fit_32(a, Bx, G)) {
         k_dist_lines<<<(unsigned)blocks, kScanLanes, 0, s>>>(maps, a.lines, Bx, a.inner, a.plane,
                                                              (int)a.stride, a.m, G);

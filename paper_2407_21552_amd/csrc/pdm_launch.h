@@ -134,7 +134,8 @@ struct CachedArgs {
     const void* bmax;
     uint8_t* dist;
     int Bx, By, Bz, bytes, nwords, levels;
-    int store_vec;
+    int store_vec;  // packed stores of 4 distances allowed
+    int load_vec;   // vector loads of 4 bricks' [min,max] allowed
 };
 
 struct PomExactArgs {

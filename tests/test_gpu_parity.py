@@ -206,6 +206,32 @@ def test_many_line_scans(pdm, orc, shape, dtype, levels, n, label):
         np.testing.assert_array_equal(got[p], want[p], err_msg=f"PDM {p}")
 
 
+FEW_LINE_SHAPES = [
+    # (voxel shape zyx, dtype, levels, n, label): y/z passes over few lines
+    # (one map, or a few) of 17 to 256 bricks: two lanes per line
+    ((132, 68, 180), np.uint8, 256, 4, "33x17x45 grid: lines of 17 and 33"),
+    ((400, 1020, 148), np.uint8, 256, 3, "100x255x37 grid: lines of 255 and 100"),
+    ((1024, 256, 80), np.uint16, 4096, 2, "256x64x20 grid: z lines of 256, u16"),
+    ((516, 964, 36), np.uint8, 256, 5, "129x241x9 grid: lines of 241 and 129"),
+    ((800, 192, 256), np.uint8, 256, 4, "200x48x64 grid: lines of 48 and 200"),
+]
+
+
+@pytest.mark.parametrize("shape,dtype,levels,n,label", FEW_LINE_SHAPES,
+                         ids=[s[-1].split(":")[0] for s in FEW_LINE_SHAPES])
+def test_few_line_scans(pdm, orc, shape, dtype, levels, n, label):
+    """Passes over few lines of 17..256 bricks (a handful of PDMs, the plain
+    method's one map and the cached-range one): every PDM, D' and both D
+    against the oracle for a few TFs, with ragged line counts (the last pair
+    tile partly past the last line) and an empty partition."""
+    import torch
+    vol = blocky(shape, dtype, levels, seed=sum(shape) + 7 * n, keep=0.02, cell=5)
+    vol = (vol % (levels * 3 // 4)).astype(dtype)  # the top partition stays empty
+    bounds = W.uniform_bounds(levels, n)
+    say(f"[case] few-line scans {label}: shape={vol.shape} n={n}")
+    run_all(pdm, orc, vol, levels, bounds, tfs(levels, 4, sum(shape)), label)
+
+
 MAX_SHAPES = [
     # (shape zyx, dtype, levels, n, label): grids at the ABI's axis limits
     ((3, 5, 4 * 16384), np.uint8, 256, 16, "x at the limit: 16384 bricks, 64 wave segments"),

@@ -130,3 +130,91 @@ def test_longer_lines_with_wide_table():
     for m in (257, 300):
         f = np.where(rng.random(m) < 0.02, 0, 255)
         np.testing.assert_array_equal(two_sided(f), brute(f))
+
+
+def _padded_words(f, nch):
+    """A line as the register kernels hold it: 4*nch words of 4 bytes, the
+    positions past the line repeating its last value."""
+    last = len(f) - 1
+    return [[int(f[min(4 * r + k, last)]) for k in range(4)] for r in range(4 * nch)]
+
+
+def registers_one_lane(f):
+    """The one-lane register kernel: the line padded to whole chunks of 16,
+    a forward pass from a start state above every value, then a backward
+    pass from the padded end (positions counted from it), stores of padded
+    positions sent to the last position before its own store."""
+    m = len(f)
+    nch = -(-m // 16)
+    pend = 16 * nch - 1
+    w = _padded_words(f, nch)
+    fwd = Lane(258, 511)
+    for p in range(pend + 1):
+        w[p // 4][p % 4] = fwd.step(p, w[p // 4][p % 4])
+    bwd = Lane(258, 511)
+    out = [None] * m
+    for p in range(pend, -1, -1):
+        out[min(p, m - 1)] = bwd.step(pend - p, w[p // 4][p % 4])
+    return np.array(out)
+
+
+def registers_pairs(f):
+    """The two-lane register kernel: both lanes load the padded line, the
+    upper lane reverses it (register r, byte k = position pend - 4r - k);
+    phase 1 runs steps 0 .. H-1 (registers 0 .. 2*nch-1) on each lane's own
+    data; the lanes swap halves (register r >= 2*nch takes the other lane's
+    register 4*nch-1-r, byte-reversed); phase 2 runs steps H .. 2H-1; the
+    upper lane's results are brought back into order and stored at positions
+    0 .. H-1, the lower lane's at H .. pend, last first."""
+    m = len(f)
+    nch = -(-m // 16)
+    NW, H = 4 * nch, 8 * nch
+    assert nch >= 2
+    lo, up = _padded_words(f, nch), _padded_words(f, nch)
+    for j in range(NW // 2):
+        a, b = up[j], up[NW - 1 - j]
+        up[j], up[NW - 1 - j] = b[::-1], a[::-1]
+    L, U = Lane(258, 511), Lane(258, 511)
+
+    def phase(r0, r1):
+        for r in range(r0, r1):
+            for k in range(4):
+                s = 4 * r + k
+                lo[r][k] = L.step(s, lo[r][k])
+                up[r][k] = U.step(s, up[r][k])
+
+    phase(0, NW // 2)
+    assert 4 * (NW // 2) == H
+    for r in range(NW // 2, NW):
+        lo[r], up[r] = up[NW - 1 - r][::-1], lo[NW - 1 - r][::-1]
+    phase(NW // 2, NW)
+    for j in range(NW // 2):
+        up[j] = up[NW - 1 - j][::-1]
+    out = [None] * m
+    for r in range(NW // 2):
+        for k in range(4):
+            assert 4 * r + k < m
+            out[4 * r + k] = up[r][k]
+    for r in range(NW - 1, NW // 2 - 1, -1):
+        for k in range(3, -1, -1):
+            out[min(4 * r + k, m - 1)] = lo[r][k]
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_register_kernels_match_definition(seed):
+    for f in lines(seed, 300):
+        np.testing.assert_array_equal(registers_one_lane(f), brute(f), err_msg=str(list(f)))
+        if len(f) > 16:
+            np.testing.assert_array_equal(registers_pairs(f), brute(f), err_msg=str(list(f)))
+
+
+def test_register_kernels_every_chunk_count():
+    # every line length 17..256 (odd and even chunk counts, the split point
+    # at 8*nch), sparse and dense lines
+    rng = np.random.default_rng(21)
+    for m in range(2, 257):
+        for f in (np.where(rng.random(m) < 0.04, 0, 255), rng.integers(0, 256, m)):
+            np.testing.assert_array_equal(registers_one_lane(f), brute(f), err_msg=f"m={m}")
+            if m > 16:
+                np.testing.assert_array_equal(registers_pairs(f), brute(f), err_msg=f"m={m}")
