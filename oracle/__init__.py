@@ -22,21 +22,29 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PDM_ORACLE_LIB names a prebuilt oracle to load instead (the sanitizer test
+# builds one with -fsanitize=address,undefined and runs the pins against it)
+_LIB = os.environ.get("PDM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+FLAGS = ["-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared"]
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
 
 RANGE = 0
 EXACT = 1
 CAP = 255
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP) into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                        _SRC, "-o", tmp], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, out: str = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP) into ``oracle/liboracle.so`` (or
+    `out`); with `sanitize`, instrumented for AddressSanitizer and
+    UndefinedBehaviorSanitizer."""
+    target = out or _LIB
+    if force or not os.path.exists(target):
+        tmp = target + ".tmp"
+        flags = FLAGS + (SANITIZE_FLAGS if sanitize else [])
+        subprocess.run(["gcc"] + flags + [_SRC, "-o", tmp], check=True)
+        os.replace(tmp, target)
+    return target
 
 
 _lib = None
@@ -45,7 +53,8 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if "PDM_ORACLE_LIB" not in os.environ and (
+                not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p

@@ -434,6 +434,12 @@ EXACT_SHAPES = [
     ((9, 14, 1024), np.uint8, 256, 64, "x rows of 256 bricks"),
     ((3, 1030, 6), np.uint8, 256, 3, "y lines over 256 bricks"),
     ((64, 64, 68), np.uint8, 256, 8, "x not a multiple of 16"),
+    # rows of 33-128 bricks packed 16 or 32 lanes per row, with a row count
+    # (By*Bz) that is not a multiple of the rows per wave
+    ((9, 11, 200), np.uint8, 256, 16, "50-brick rows, 16 lanes per row, u8"),
+    ((10, 11, 198), np.uint16, 4096, 32, "50-brick rows, 16 lanes per row, u16"),
+    ((17, 9, 500), np.uint8, 256, 32, "125-brick rows, 32 lanes per row, u8"),
+    ((19, 10, 503), np.uint16, 4096, 64, "126-brick rows, 32 lanes per row, u16"),
 ]
 
 
