@@ -390,9 +390,9 @@ def main():
         return r
 
     total_by_kernel = {
-        "k_plain_x": sum(plx_ms), "y/z scans, one map (k_dist_axis + k_dist_split)": sum(dyz1_ms) + sum(cyz_ms),
+        "k_plain_x": sum(plx_ms), "y/z scans, one map (k_dist_pairs)": sum(dyz1_ms) + sum(cyz_ms),
         "k_combine": sum(upd_ms), "k_plain_cached_x": sum(cx_ms), "k_bricks": sum(bricks_ms),
-        "k_pom_x": sum(pomx_ms), "y/z scans, all partitions (k_dist_global)": sum(dyz_n_ms)}
+        "k_pom_x": sum(pomx_ms), "y/z scans, all partitions (k_dist_lines)": sum(dyz_n_ms)}
 
     def ms_stats(xs):
         return {"p50_ms": round(pct(xs, 50), 4), "p90_ms": round(pct(xs, 90), 4),
@@ -878,18 +878,24 @@ def run_configs(args):
             return ([x.elapsed_time(y) for x, y, _ in out], [y.elapsed_time(z) for _, y, z in out])
 
         upd = lambda a: pdm.tf_update(desc, v.pdms, bounds, a, v.dist, stream)
+        cached = lambda a: pdm.full_recompute_cached(desc, v.bmin, v.bmax, a, d_full, stream)
+        cached_b = [2 * G * s + G] * T
         timed(False, upd)  # warm-up
+        timed(False, cached)
         rec = {}
         for mode in ("warm", "cold"):
             log(f"{name}: {T} TFs, {mode} ...")
             u = timed(mode == "cold", upd)
             ox, yz = full_phases(mode == "cold")
             fm = [a + b for a, b in zip(ox, yz)]
+            cm = timed(mode == "cold", cached)
             rec[mode] = {"tf_update": stats(u, upd_b, small),
                          "full_recompute": {**stats(fm, full_b, small),
                                             "occupancy_x_mean_ms": round(float(np.mean(ox)), 4),
                                             "distance_yz_mean_ms": round(float(np.mean(yz)), 4)},
-                         "speedup_p50": round(pct(fm, 50) / pct(u, 50), 2)}
+                         "full_recompute_cached": stats(cm, cached_b, True),
+                         "speedup_p50": round(pct(fm, 50) / pct(u, 50), 2),
+                         "speedup_vs_cached_p50": round(pct(cm, 50) / pct(u, 50), 2)}
         # EXACT reading (occupancy from the brick's voxels): build, full
         # recompute warm and cold, and the update over the EXACT PDMs; and how
         # much larger its distances run than RANGE's (EXACT occupancy is a

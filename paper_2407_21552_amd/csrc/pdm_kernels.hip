@@ -858,19 +858,21 @@ __global__ void __launch_bounds__(256) k_plain_exact_x(const T* __restrict__ vol
 // for v+1 at the next position, so both choices advance again there.  An
 // empty entry (0) behaves the same way.
 //
-// Each step writes last[f(i)] = i and then reads last[F(i)+1] for the next
-// step; the read comes after the write, so it sees it.  Reading the next
-// step's candidates ahead (to keep the read off the chain between steps)
-// measured slower: the extra reads and selects cost more issue time than the
-// wait they removed.
+// With that rule the witness after each step is always last[F(i)], read
+// after the step's own write last[f(i)] = i: a new minimum (f(i) <= X) makes
+// i the witness, and last[f(i)] = i was just written; an advance takes
+// last[v+1], which the write did not touch (f(i) > v+1); otherwise v and W
+// stay, and last[v] was not touched either (f(i) > v).  So a step is one
+// table write, X = min(v+1, max(v, i-W)), F(i) = min(f(i), X) and one table
+// read W = last[F(i)]: no selects between witness candidates.
 //
-// Tables: 258 rows (values 0..257, the last two never written) of kPitch
-// entries, lane-major inside a row; the odd dword pitch (17) spreads lanes
-// that look up different values over the LDS banks.
+// Tables: rows for the values 0..255 (F(i) <= 255 from the first step on) of
+// kPitch entries, lane-major inside a row; the odd dword pitch (17) spreads
+// lanes that look up different values over the LDS banks.
 // ---------------------------------------------------------------------------
 constexpr int kScanLanes = 64;
 constexpr int kPitch = 68;      // entries per table row (>= kScanLanes)
-constexpr int kRows = 258;
+constexpr int kRows = 256;
 constexpr int kMaxLine = 256;   // longest line staged in LDS
 // Passes over at most this many lines use the LDS-staged kernel: they cannot
 // fill the chip's 1024 SIMDs with more than a few waves each, so per-wave
@@ -893,20 +895,18 @@ __device__ __forceinline__ void clear_table(P* tbl) {
     for (int i = threadIdx.x; i < kBytes / 16; i += kScanLanes) t4[i] = make_uint4(0, 0, 0, 0);
 }
 
-// One step of the one-sided pass at position i (i >= 1) with input fi.
-// State: v = F(i-1), W its witness, t = last[v+1].  Table offsets are
-// 32-bit: v stays below 2^8 (an unsigned min with the 8-bit input), so rows
-// times kPitch plus the lane stays far below 2^24.
+// One step of the one-sided pass at position i with input fi.  State:
+// v = F(i-1) and its witness W = last[v]; the first step of a pass starts
+// from v above every value (511), so it takes F = f(0) with witness 0.
+// Table offsets are 32-bit: v stays below 2^8 after the unsigned min with
+// the 8-bit input, so rows times kPitch plus the lane stays far below 2^24.
 #define PDM_SCAN_STEP(i_, fi_, out_)                                              \
     {                                                                             \
         const int i__ = (i_), fi__ = (fi_);                                       \
         tbl[__umul24((unsigned)fi__, (unsigned)kPitch) + (unsigned)lane] = (P)i__; \
-        const bool adv__ = (i__ - W) > v;                                         \
-        const int X__ = v + (adv__ ? 1 : 0);                                      \
-        const int Wn__ = adv__ ? t : W;                                           \
-        W = fi__ <= X__ ? i__ : Wn__;                                             \
-        v = (int)umin((unsigned)fi__, (unsigned)X__);                             \
-        t = (int)tbl[__umul24((unsigned)v + 1u, (unsigned)kPitch) + (unsigned)lane]; \
+        const unsigned X__ = umin((unsigned)v + 1u, umax((unsigned)v, (unsigned)(i__ - W))); \
+        v = (int)umin((unsigned)fi__, X__);                                       \
+        W = (int)tbl[__umul24((unsigned)v, (unsigned)kPitch) + (unsigned)lane];   \
         out_ = v;                                                                 \
     }
 
@@ -919,7 +919,7 @@ __device__ __forceinline__ void one_sided_lds(uint8_t* col, int cs, int m, P* __
     const int lane = threadIdx.x;
     // F(0) = f(0); its table entry (position 0) equals the cleared value
     int v = col[0];
-    int W = 0, t = 0;
+    int W = 0;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
@@ -946,7 +946,7 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
                                                  P* __restrict__ tbl) {
     const int lane = threadIdx.x;
     int v = active ? (int)p[0] : 0;
-    int W = 0, t = 0;
+    int W = 0;
     int c = 1;
     for (; c + CH <= m; c += CH) {
         int f[CH];
@@ -976,7 +976,7 @@ __device__ __forceinline__ void one_sided_global(BP p, int64_t step, int m, bool
 template <int CH>
 __device__ __forceinline__ void one_sided_lds_range(uint8_t* col, int cs, int ib, int ie, int vmax,
                                                     bool track, uint8_t* __restrict__ tbl, int& v,
-                                                    int& W, int& t, int& raw_min) {
+                                                    int& W, int& raw_min) {
     using P = uint8_t;  // table entry type of PDM_SCAN_STEP
     const int lane = threadIdx.x;
     int c = ib;
@@ -1102,7 +1102,7 @@ __device__ __forceinline__ void scan_lines_regs(uint8_t* base, int voff, int str
     __syncthreads();  // work-groups of the callers are one wave
     // forward pass; the first step starts from "no candidate yet" (v above
     // every value), so it takes f(0) with witness 0 like every later one
-    int v = 511, W = 0, t = 0;
+    int v = 511, W = 0;
 #pragma unroll
     for (int c = 0; c < kLineChunks; ++c) {
         if (c < nch) {
@@ -1130,7 +1130,6 @@ __device__ __forceinline__ void scan_lines_regs(uint8_t* base, int voff, int str
     const int pend = kLineChunk * nch - 1;
     v = 511;
     W = 0;
-    t = 0;
 #pragma unroll
     for (int c = kLineChunks - 1; c >= 0; --c) {
         if (c < nch) {
@@ -1190,7 +1189,7 @@ __device__ __forceinline__ uint32_t byte_reverse(uint32_t w) {
 // vector register, reset every 16 steps (one add per step).
 template <int R0, int R1, int NW>
 __device__ __forceinline__ void pairs_phase(uint32_t (&w)[NW], uint8_t* __restrict__ tbl, int lane,
-                                            int& v, int& W, int& t) {
+                                            int& v, int& W) {
     using P = uint8_t;  // table entry type of PDM_SCAN_STEP
     int pc = 0;
     int pbase = 0;
@@ -1218,6 +1217,7 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
                                                            int stride, int m, int64_t G, int wide) {
     constexpr int NW = 4 * NCH;          // registers per line
     constexpr int H = 8 * NCH;           // steps per phase (half the padded line)
+    constexpr int KS = (16 * NCH + 31) / 32;  // staging rounds of 32 positions
     // the table; before and after the passes also the staging tile [pos][32]
     __shared__ __align__(16) uint8_t tbl[(kRows * kPitch + 15) & ~15];
     static_assert(32 * kMaxLine <= (int)sizeof(tbl), "the staging tile fits in the table's space");
@@ -1238,10 +1238,16 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
         // the 32 lines are x0 .. x0+31 of one row and rows are 16-byte
         // aligned: stage the tile with 16-byte pieces (two per position),
         // then each lane gathers its column
+        // (all pieces in flight at once; rows past the line repeat row m-1)
         const int q = lane & 1;
-        for (int r = lane >> 1; r < m; r += 32)
-            *reinterpret_cast<uint4*>(&tbl[r * 32 + 16 * q]) =
-                *reinterpret_cast<const uint4*>(maps + base + (int64_t)r * stride + 16 * q);
+        uint4 piece[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            piece[k] = *reinterpret_cast<const uint4*>(
+                maps + base + (int64_t)min((lane >> 1) + 32 * k, last) * stride + 16 * q);
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            *reinterpret_cast<uint4*>(&tbl[((lane >> 1) + 32 * k) * 32 + 16 * q]) = piece[k];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NW; ++r) {
@@ -1273,16 +1279,16 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
     }
     clear_table<uint8_t>(tbl);
     __syncthreads();
-    int v = 511, W = 0, t = 0;
+    int v = 511, W = 0;
     // phase 1: steps 0 .. H-1 (registers 0 .. NW/2-1) over the lane's own half
-    pairs_phase<0, NW / 2>(w, tbl, lane, v, W, t);
+    pairs_phase<0, NW / 2>(w, tbl, lane, v, W);
     // swap halves: register r (r >= NW/2) takes the other lane's register
     // NW-1-r, reversed into this lane's order
 #pragma unroll
     for (int r = NW / 2; r < NW; ++r)
         w[r] = byte_reverse((uint32_t)__shfl_xor((int)w[NW - 1 - r], 32, kScanLanes));
     // phase 2: steps H .. 2H-1 (registers NW/2 .. NW-1) over the other lane's results
-    pairs_phase<NW / 2, NW>(w, tbl, lane, v, W, t);
+    pairs_phase<NW / 2, NW>(w, tbl, lane, v, W);
     // the lower lane holds positions H .. pend in order; the upper lane
     // positions 0 .. H-1 reversed, brought into order in registers 0 .. NW/2-1
 #pragma unroll
@@ -1306,9 +1312,15 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
         }
         __syncthreads();
         const int q = lane & 1;
-        for (int r = lane >> 1; r < m; r += 32)
-            *reinterpret_cast<uint4*>(maps + base + (int64_t)r * stride + 16 * q) =
-                *reinterpret_cast<const uint4*>(&tbl[r * 32 + 16 * q]);
+        uint4 piece[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            piece[k] = *reinterpret_cast<const uint4*>(&tbl[((lane >> 1) + 32 * k) * 32 + 16 * q]);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int r = (lane >> 1) + 32 * k;
+            if (r < m) *reinterpret_cast<uint4*>(maps + base + (int64_t)r * stride + 16 * q) = piece[k];
+        }
     } else if (upper) {
         // positions 0 .. H-1: all inside the line (m > 16*(NCH-1) >= H for NCH >= 2)
 #pragma unroll
@@ -1428,18 +1440,18 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__
     const int cs = half == 0 ? 32 : -32;
     int raw_min = col[0];
     int v = min(raw_min, vmax);
-    int W = 0, t = 0;
+    int W = 0;
     // phase 1: forward lanes steps [1, h), backward lanes [1, m - h)
-    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, t, raw_min);
+    one_sided_lds_range<16>(col, cs, 1, h, vmax, true, tbl, v, W, raw_min);
     if (m - h > h && half == 1)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, t, raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, true, tbl, v, W, raw_min);
     __builtin_amdgcn_wave_barrier();
     const int lmin = min(raw_min, __shfl_xor(raw_min, 32, kScanLanes));
     // phase 2: forward lanes steps [h, m), backward lanes [m - h, m)
     if (m - h > h && half == 0)
-        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, t, raw_min);
+        one_sided_lds_range<1>(col, cs, h, h + 1, vmax, false, tbl, v, W, raw_min);
     __builtin_amdgcn_wave_barrier();
-    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, t, raw_min);
+    one_sided_lds_range<16>(col, cs, m - h, m, vmax, false, tbl, v, W, raw_min);
     // every value of the line >= vmax: the two-sided result is the minimum
     if (lmin >= vmax) {
         const int n = half == 0 ? m - h : h;  // this lane's phase-2 positions

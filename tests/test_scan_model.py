@@ -6,10 +6,11 @@ recurrence of the separable chessboard distance transform, Sec. 3.1).  The
 kernels run it as a forward one-sided pass F(i) = min_{j<=i} max(i-j, f(j))
 followed by the same pass backwards over F, each in one sweep that keeps
 v = F(i-1), a witness W and a table last[w] of the latest position holding
-value w.  Each step writes its own entry first and then reads last[F(i)+1]
-for the next step (so the read sees the write); on an advance the witness
-becomes that table entry alone, with no max against the old witness.  The
-split variant runs the forward and backward passes at once on two lanes, each
+value w.  On an advance the witness becomes the table entry last[v+1] alone,
+with no max against the old witness; with that rule the witness after every
+step equals last[F(i)] read after the step's own write, so each step writes
+last[f(i)] = i, sets F(i) = min(f(i), min(v+1, max(v, i-W))) and reads
+W = last[F(i)].  The split variant runs the forward and backward passes at once on two lanes, each
 first over its half of the line and then over the half the other has done,
 with values clamped at min(m, 255) and the line's minimum as the result
 wherever every value is at least that clamp.  These models mirror that logic
@@ -25,25 +26,42 @@ def brute(f):
 
 
 class Lane:
-    """One lane's scan state: v = F(i-1), the witness W and t = last[v+1]."""
+    """One lane's scan state: v = F(i-1) and its witness W = last[v]."""
 
     def __init__(self, rows, v0):
         self.tbl = [0] * rows
-        self.v, self.W, self.t = v0, 0, 0
+        self.v, self.W = v0, 0
 
     def step(self, i, fi):
         self.tbl[fi] = i
         v = self.v
-        adv = (i - self.W) > v
-        X = v + (1 if adv else 0)
-        Wn = self.t if adv else self.W
-        self.W = i if fi <= X else Wn
+        X = min(v + 1, max(v, i - self.W))
         self.v = min(fi, X)
-        self.t = self.tbl[self.v + 1]
+        self.W = self.tbl[self.v]
         return self.v
 
 
-def one_sided(col, rows=258):
+class SelectLane:
+    """The same pass with the witness chosen among its candidates: position
+    i on a new minimum, last[v+1] (read before the step's write) on an
+    advance, else the old witness."""
+
+    def __init__(self, rows, v0):
+        self.tbl = [0] * rows
+        self.v, self.W = v0, 0
+
+    def step(self, i, fi):
+        v = self.v
+        adv = (i - self.W) > v
+        X = v + (1 if adv else 0)
+        cand = self.tbl[v + 1] if v + 1 < len(self.tbl) else 0
+        self.tbl[fi] = i
+        self.W = i if fi <= X else (cand if adv else self.W)
+        self.v = min(fi, X)
+        return self.v
+
+
+def one_sided(col, rows=256):
     lane = Lane(rows, col[0])
     out = [col[0]]
     for i in range(1, len(col)):
@@ -117,6 +135,17 @@ def test_split_scan_matches_definition(seed):
         np.testing.assert_array_equal(split(f), brute(f), err_msg=str(list(f)))
 
 
+def test_witness_is_the_table_entry_of_the_value():
+    # the step that reads W = last[F(i)] keeps the same witness as the rule
+    # that picks among i, last[v+1] and the old witness, at every step
+    for seed in (5, 6):
+        for f in lines(seed, 200):
+            a, b = Lane(257, 511), SelectLane(257, 511)
+            for i, fi in enumerate(int(x) for x in f):
+                assert a.step(i, fi) == b.step(i, fi)
+                assert a.W == b.W, (list(f), i)
+
+
 def test_scan_edge_lines():
     for f in ([0], [255], [7], [0, 255], [255, 0], [3, 3], [255] * 256, [0] * 256,
               [255] * 255 + [0], [0] + [255] * 255, list(range(256)), list(range(255, -1, -1))):
@@ -148,10 +177,10 @@ def registers_one_lane(f):
     nch = -(-m // 16)
     pend = 16 * nch - 1
     w = _padded_words(f, nch)
-    fwd = Lane(258, 511)
+    fwd = Lane(256, 511)
     for p in range(pend + 1):
         w[p // 4][p % 4] = fwd.step(p, w[p // 4][p % 4])
-    bwd = Lane(258, 511)
+    bwd = Lane(256, 511)
     out = [None] * m
     for p in range(pend, -1, -1):
         out[min(p, m - 1)] = bwd.step(pend - p, w[p // 4][p % 4])
@@ -174,7 +203,7 @@ def registers_pairs(f):
     for j in range(NW // 2):
         a, b = up[j], up[NW - 1 - j]
         up[j], up[NW - 1 - j] = b[::-1], a[::-1]
-    L, U = Lane(258, 511), Lane(258, 511)
+    L, U = Lane(256, 511), Lane(256, 511)
 
     def phase(r0, r1):
         for r in range(r0, r1):
