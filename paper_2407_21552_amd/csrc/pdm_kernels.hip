@@ -1234,11 +1234,16 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
     const int last = m - 1;
     uint32_t w[NW];
     uint32_t all = 0xFFFFFFFFu;
+    // wide: the tile passes through LDS in slots of 32 bytes (one position of
+    // the 32 lines): slot s < H holds position s, slot H + s position pend - s,
+    // so each lane reads only its half, already in its own step order, from
+    // slot (upper ? H : 0) + s
+    const int half_base = li + (upper ? 32 * H : 0);
     if (wide) {
         // the 32 lines are x0 .. x0+31 of one row and rows are 16-byte
-        // aligned: stage the tile with 16-byte pieces (two per position),
-        // then each lane gathers its column
-        // (all pieces in flight at once; rows past the line repeat row m-1)
+        // aligned: load the tile in 16-byte pieces (two per position, all in
+        // flight at once; rows past the line repeat row m-1), store them to
+        // their slots, then each lane gathers its half column
         const int q = lane & 1;
         uint4 piece[KS];
 #pragma unroll
@@ -1246,14 +1251,17 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
             piece[k] = *reinterpret_cast<const uint4*>(
                 maps + base + (int64_t)min((lane >> 1) + 32 * k, last) * stride + 16 * q);
 #pragma unroll
-        for (int k = 0; k < KS; ++k)
-            *reinterpret_cast<uint4*>(&tbl[((lane >> 1) + 32 * k) * 32 + 16 * q]) = piece[k];
+        for (int k = 0; k < KS; ++k) {
+            const int r = (lane >> 1) + 32 * k;
+            const int slot = r < H ? r : 3 * H - 1 - r;
+            if (r < 2 * H) *reinterpret_cast<uint4*>(&tbl[slot * 32 + 16 * q]) = piece[k];
+        }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NW; ++r) {
+        for (int r = 0; r < NW / 2; ++r) {
             uint32_t b[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b[k] = tbl[min(4 * r + k, last) * 32 + li];
+            for (int k = 0; k < 4; ++k) b[k] = tbl[half_base + (4 * r + k) * 32];
             w[r] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
             all &= w[r];
         }
@@ -1268,15 +1276,11 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
             w[r] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
             all &= w[r];
         }
+        // the upper lane's half in backward order
+#pragma unroll
+        for (int j = 0; j < NW / 2; ++j) w[j] = upper ? byte_reverse(w[NW - 1 - j]) : w[j];
     }
     if (__ballot(all != 0xFFFFFFFFu) == 0ull) return;  // every byte 255: nothing changes
-    // the upper lane's copy in backward order
-#pragma unroll
-    for (int j = 0; j < NW / 2; ++j) {
-        const uint32_t a = w[j], b = w[NW - 1 - j];
-        w[j] = upper ? byte_reverse(b) : a;
-        w[NW - 1 - j] = upper ? byte_reverse(a) : b;
-    }
     clear_table<uint8_t>(tbl);
     __syncthreads();
     int v = 511, W = 0;
@@ -1289,39 +1293,39 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_pairs(uint8_t* __restrict__
         w[r] = byte_reverse((uint32_t)__shfl_xor((int)w[NW - 1 - r], 32, kScanLanes));
     // phase 2: steps H .. 2H-1 (registers NW/2 .. NW-1) over the other lane's results
     pairs_phase<NW / 2, NW>(w, tbl, lane, v, W);
-    // the lower lane holds positions H .. pend in order; the upper lane
-    // positions 0 .. H-1 reversed, brought into order in registers 0 .. NW/2-1
-#pragma unroll
-    for (int j = 0; j < NW / 2; ++j) w[j] = byte_reverse(w[NW - 1 - j]);
+    // the lower lane holds positions H .. pend in order (step H + s is
+    // position H + s); the upper lane positions H-1 .. 0 (step H + s is
+    // position H - 1 - s)
     if (wide) {
-        // back through the tile: each lane writes its half's column, then
-        // the rows leave in 16-byte pieces; the lower lane writes the padded
-        // positions to row m-1 before that row's own value
+        // back through the slots: step H + s of either lane goes to slot
+        // (upper ? H : 0) + s, which holds position H + s (lower) or
+        // H - 1 - s (upper); rows leave in 16-byte pieces, positions of the
+        // padding are never stored
         __syncthreads();  // every lane is done with the table
-        if (upper) {
 #pragma unroll
-            for (int r = 0; r < NW / 2; ++r)
+        for (int r = NW / 2; r < NW; ++r)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) tbl[(4 * r + k) * 32 + li] = (uint8_t)(w[r] >> (8 * k));
-        } else {
-#pragma unroll
-            for (int r = NW - 1; r >= NW / 2; --r)
-#pragma unroll
-                for (int k = 3; k >= 0; --k)
-                    tbl[min(4 * r + k, last) * 32 + li] = (uint8_t)(w[r] >> (8 * k));
-        }
+            for (int k = 0; k < 4; ++k)
+                tbl[half_base + (4 * (r - NW / 2) + k) * 32] = (uint8_t)(w[r] >> (8 * k));
         __syncthreads();
         const int q = lane & 1;
         uint4 piece[KS];
 #pragma unroll
-        for (int k = 0; k < KS; ++k)
-            piece[k] = *reinterpret_cast<const uint4*>(&tbl[((lane >> 1) + 32 * k) * 32 + 16 * q]);
+        for (int k = 0; k < KS; ++k) {
+            const int r = min((lane >> 1) + 32 * k, 2 * H - 1);
+            const int slot = r >= H ? r - H : 2 * H - 1 - r;
+            piece[k] = *reinterpret_cast<const uint4*>(&tbl[slot * 32 + 16 * q]);
+        }
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int r = (lane >> 1) + 32 * k;
             if (r < m) *reinterpret_cast<uint4*>(maps + base + (int64_t)r * stride + 16 * q) = piece[k];
         }
-    } else if (upper) {
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < NW / 2; ++j) w[j] = byte_reverse(w[NW - 1 - j]);
+    if (upper) {
         // positions 0 .. H-1: all inside the line (m > 16*(NCH-1) >= H for NCH >= 2)
 #pragma unroll
         for (int r = 0; r < NW / 2; ++r)

@@ -214,6 +214,9 @@ FEW_LINE_SHAPES = [
     ((1024, 256, 80), np.uint16, 4096, 2, "256x64x20 grid: z lines of 256, u16"),
     ((516, 964, 36), np.uint8, 256, 5, "129x241x9 grid: lines of 241 and 129"),
     ((800, 192, 256), np.uint8, 256, 4, "200x48x64 grid: lines of 48 and 200"),
+    # rows of 32 and 64 bricks: the tile passes through LDS slots
+    ((128, 400, 128), np.uint8, 256, 3, "32x100x32 grid: LDS slots, lines of 100 and 32"),
+    ((68, 68, 256), np.uint8, 256, 3, "17x17x64 grid: LDS slots, lines of 17"),
 ]
 
 

@@ -230,12 +230,54 @@ def registers_pairs(f):
     return np.array(out)
 
 
+def registers_pairs_slots(f):
+    """The two-lane register kernel on rows that are staged through LDS: the
+    tile's positions go to slots of one position each, slot s < H holding
+    position s and slot H + s position pend - s (positions past the line
+    repeat its last value); the lower lane reads slots 0 .. H-1 and the upper
+    lane slots H .. 2H-1, each already in its own step order; phases and swap
+    as in registers_pairs; step H + s of the lower lane goes back to slot s
+    (position H + s) and of the upper lane to slot H + s (position H-1-s),
+    from where the positions below m are stored."""
+    m = len(f)
+    nch = -(-m // 16)
+    NW, H = 4 * nch, 8 * nch
+    assert nch >= 2 and H <= m
+    ks = (16 * nch + 31) // 32
+    slots = [None] * (2 * H)
+    for r in range(32 * ks):
+        if r < 2 * H:
+            slots[r if r < H else 3 * H - 1 - r] = int(f[min(r, m - 1)])
+    lo = [[slots[4 * j + k] for k in range(4)] for j in range(NW // 2)] + [None] * (NW // 2)
+    up = [[slots[H + 4 * j + k] for k in range(4)] for j in range(NW // 2)] + [None] * (NW // 2)
+    L, U = Lane(256, 511), Lane(256, 511)
+
+    def phase(r0, r1):
+        for r in range(r0, r1):
+            for k in range(4):
+                s = 4 * r + k
+                lo[r][k] = L.step(s, lo[r][k])
+                up[r][k] = U.step(s, up[r][k])
+
+    phase(0, NW // 2)
+    for r in range(NW // 2, NW):
+        lo[r], up[r] = up[NW - 1 - r][::-1], lo[NW - 1 - r][::-1]
+    phase(NW // 2, NW)
+    back = [None] * (2 * H)
+    for r in range(NW // 2, NW):
+        for k in range(4):
+            back[4 * (r - NW // 2) + k] = lo[r][k]
+            back[H + 4 * (r - NW // 2) + k] = up[r][k]
+    return np.array([back[r - H] if r >= H else back[2 * H - 1 - r] for r in range(m)])
+
+
 @pytest.mark.parametrize("seed", [5, 6])
 def test_register_kernels_match_definition(seed):
     for f in lines(seed, 300):
         np.testing.assert_array_equal(registers_one_lane(f), brute(f), err_msg=str(list(f)))
         if len(f) > 16:
             np.testing.assert_array_equal(registers_pairs(f), brute(f), err_msg=str(list(f)))
+            np.testing.assert_array_equal(registers_pairs_slots(f), brute(f), err_msg=str(list(f)))
 
 
 def test_register_kernels_every_chunk_count():
@@ -247,3 +289,4 @@ def test_register_kernels_every_chunk_count():
             np.testing.assert_array_equal(registers_one_lane(f), brute(f), err_msg=f"m={m}")
             if m > 16:
                 np.testing.assert_array_equal(registers_pairs(f), brute(f), err_msg=f"m={m}")
+                np.testing.assert_array_equal(registers_pairs_slots(f), brute(f), err_msg=f"m={m}")
