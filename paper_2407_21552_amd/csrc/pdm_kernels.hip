@@ -1840,14 +1840,21 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, i
     PDM_GLB T* bmin = (PDM_GLB T*)d.bmin;
     PDM_GLB T* bmax = (PDM_GLB T*)d.bmax;
     PDM_GLB uint8_t* pdms = (PDM_GLB uint8_t*)d.pdms;
+    // descriptor fields in registers: the map stores below could alias the
+    // descriptor as far as the compiler knows, which would reload them per
+    // partition
     const int W = d.row_lanes;
+    const int n = d.n, Bx = d.Bx, By = d.By;
+    const int64_t G = d.G;
+    const bool vec = d.store_vec != 0;
+    const PDM_GLB int32_t* bounds = (const PDM_GLB int32_t*)d.bounds;
     const int q = lane & (W - 1);
     const int per = kWave / W;
-    const int nb_row = max(0, min(4, d.Bx - 4 * q));
+    const int nb_row = max(0, min(4, Bx - 4 * q));
     for (int row0 = by0; row0 < by1; row0 += per) {
         const int by = row0 + lane / W;
         const int nb = by < by1 ? nb_row : 0;
-        const int64_t rbase = ((int64_t)bz * d.By + by) * d.Bx + 4 * q;
+        const int64_t rbase = ((int64_t)bz * By + by) * Bx + 4 * q;
         uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         uint32_t mx[4] = {0u, 0u, 0u, 0u};
         if (nb > 0) {
@@ -1861,13 +1868,15 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, i
                     bmax[rbase + k] = (T)r.mx[k];
                 }
         }
-        for (int p = 0; p < d.n; ++p) {
-            const uint32_t lo = (uint32_t)d.bounds[p], hi = (uint32_t)d.bounds[p + 1] - 1u;
+        uint32_t lo = (uint32_t)bounds[0];
+        for (int p = 0; p < n; ++p) {
+            const uint32_t next = (uint32_t)bounds[p + 1], hi = next - 1u;
             uint32_t o = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
             const uint32_t packed = x_distances_rows(o, lane, W);
-            if (nb > 0) store_quad(pdms + (int64_t)p * d.G, rbase, nb, packed, d.store_vec);
+            if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase, nb, packed, vec);
+            lo = next;
         }
     }
 }
