@@ -144,7 +144,6 @@ pdm_status pdm_build_bricks(const pdm_volume* v, const void* d_volume, void* d_b
     a.Bz = g.bz;
     a.bytes = v->dtype;
     a.levels = v->levels;
-    a.store_vec = g.bx % 4 == 0 && aligned(d_bmin, 4 * v->dtype) && aligned(d_bmax, 4 * v->dtype);
     // the range flag is only needed when the dtype can hold values >= levels
     if (v->levels == (v->dtype == PDM_U8 ? 256 : 65536)) a.range_err = nullptr;
     return from_hip(pdm::launch_bricks(a, stream));

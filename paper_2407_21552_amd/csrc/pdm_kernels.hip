@@ -110,152 +110,194 @@ struct QuadMinMax {
     uint32_t mn[4], mx[4];
 };
 
+// 4 and 8 bytes from any byte address (one load each; see load16).
+template <typename VP>
+__device__ __forceinline__ uint32_t load4(VP p) {
+    uint32_t w;
+    __builtin_memcpy(&w, p, 4);
+    return w;
+}
+template <typename VP>
+__device__ __forceinline__ uint2 load8(VP p) {
+    uint2 w;
+    __builtin_memcpy(&w, p, 8);
+    return w;
+}
+
+// The quad's 16 voxel rows, x in [x0, x0 + 16) inside the row: row i is
+// (z0 + i/4, y0 + i%4).  With CLAMP (a brick layer cut by the volume's end
+// in z or y) rows past the volume repeat its last row, which never changes a
+// brick's min or max; every load is issued before the first use.
+template <typename T, bool CLAMP, typename VP>
+__device__ __forceinline__ QuadMinMax<T> quad_whole_rows(VP __restrict__ vol, int nx, int ny,
+                                                         int z0, int y0, int zn, int yn, int x0) {
+    QuadMinMax<T> r;
+    auto off = [&](int i) -> int64_t {
+        const int zz = CLAMP ? min(i >> 2, zn - 1) : (i >> 2);
+        const int yy = CLAMP ? min(i & 3, yn - 1) : (i & 3);
+        return ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+    };
+    if constexpr (sizeof(T) == 1) {
+        u32x4 w[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) w[i] = load16_nt(vol + off(i));
+        // even/odd byte lanes held as packed u16 pairs, one pair per brick
+        uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t ws[4] = {w[i].x, w[i].y, w[i].z, w[i].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
+                mnE[k] = pk_min16(mnE[k], e);
+                mnO[k] = pk_min16(mnO[k], o);
+                mxE[k] = pk_max16(mxE[k], e);
+                mxO[k] = pk_max16(mxO[k], o);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t a = pk_min16(mnE[k], mnO[k]);
+            const uint32_t b = pk_max16(mxE[k], mxO[k]);
+            r.mn[k] = umin(lo16(a), hi16(a));
+            r.mx[k] = umax(lo16(b), hi16(b));
+        }
+    } else {
+        // u16: 32 bytes per row; two rounds of 8 rows (16 loads each)
+        uint32_t mn[4], mx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            u32x4 w[16];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t o = off(8 * h + i);
+                w[2 * i] = load16_nt(vol + o);
+                w[2 * i + 1] = load16_nt(vol + o + 8);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t ws[8] = {w[2 * i].x, w[2 * i].y, w[2 * i].z, w[2 * i].w,
+                                        w[2 * i + 1].x, w[2 * i + 1].y, w[2 * i + 1].z, w[2 * i + 1].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
+                    mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
+            r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
+        }
+    }
+    return r;
+}
+
+// The quad's rows when its 16 voxels run past the row end (nx >= 4): brick
+// k's 4 voxels are loaded at min(x0 + 4k, nx - 4), so every load stays in
+// the row; when that start is pulled back, its first voxels belong to the
+// brick before and are masked out (to the maximum value for the min, to 0
+// for the max).  Bricks wholly past the row end get unspecified results.
+// Rows past the volume repeat its last row, as above.
+template <typename T, typename VP>
+__device__ __forceinline__ QuadMinMax<T> quad_ragged_rows(VP __restrict__ vol, int nx, int ny,
+                                                          int z0, int y0, int zn, int yn, int x0) {
+    QuadMinMax<T> r;
+    int pos[4];
+    uint32_t mlo[4], mhi[4];  // voxels of the brick before: bits set in the loaded words
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = x0 + 4 * k;
+        pos[k] = min(x, nx - 4);
+        const int lead = min(x - pos[k], 3);
+        const uint64_t m = lead ? (~0ull >> (64 - 8 * (int)sizeof(T) * lead)) : 0ull;
+        mlo[k] = (uint32_t)m;
+        mhi[k] = (uint32_t)(m >> 32);
+    }
+    uint32_t mnA[4], mnB[4], mxA[4], mxB[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { mnA[k] = mnB[k] = 0xFFFFFFFFu; mxA[k] = mxB[k] = 0u; }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t row = ((int64_t)(z0 + min(i >> 2, zn - 1)) * ny + (y0 + min(i & 3, yn - 1))) * nx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (sizeof(T) == 1) {
+                const uint32_t w = load4(vol + row + pos[k]);
+                const uint32_t lo = w | mlo[k], hi = w & ~mlo[k];
+                mnA[k] = pk_min16(mnA[k], even_bytes(lo));
+                mnB[k] = pk_min16(mnB[k], odd_bytes(lo));
+                mxA[k] = pk_max16(mxA[k], even_bytes(hi));
+                mxB[k] = pk_max16(mxB[k], odd_bytes(hi));
+            } else {
+                const uint2 w = load8(vol + row + pos[k]);
+                mnA[k] = pk_min16(mnA[k], pk_min16(w.x | mlo[k], w.y | mhi[k]));
+                mxA[k] = pk_max16(mxA[k], pk_max16(w.x & ~mlo[k], w.y & ~mhi[k]));
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t a = pk_min16(mnA[k], mnB[k]);
+        const uint32_t b = pk_max16(mxA[k], mxB[k]);
+        r.mn[k] = umin(lo16(a), hi16(a));
+        r.mx[k] = umax(lo16(b), hi16(b));
+    }
+    return r;
+}
+
 template <typename T, typename VP>
 __device__ __forceinline__ QuadMinMax<T> quad_minmax(VP __restrict__ vol, int nx, int ny, int nz,
                                                      int q, int by, int bz) {
-    QuadMinMax<T> r;
     const int x0 = 16 * q;
     const int z0 = 4 * bz, y0 = 4 * by;
     const int zn = min(4, nz - z0), yn = min(4, ny - y0);
-    if (zn == 4 && yn == 4 && x0 + 16 <= nx) {
-        // a full quad: every row load is issued before the first use
-        const int64_t base = ((int64_t)z0 * ny + y0) * nx + x0;
-        if constexpr (sizeof(T) == 1) {
-            u32x4 w[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                w[i] = load16_nt(vol + base + ((int64_t)(i >> 2) * ny + (i & 3)) * nx);
-            uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint32_t ws[4] = {w[i].x, w[i].y, w[i].z, w[i].w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
-                    mnE[k] = pk_min16(mnE[k], e);
-                    mnO[k] = pk_min16(mnO[k], o);
-                    mxE[k] = pk_max16(mxE[k], e);
-                    mxO[k] = pk_max16(mxO[k], o);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t a = pk_min16(mnE[k], mnO[k]);
-                const uint32_t b = pk_max16(mxE[k], mxO[k]);
-                r.mn[k] = umin(lo16(a), hi16(a));
-                r.mx[k] = umax(lo16(b), hi16(b));
-            }
-        } else {
-            // u16: 32 bytes per row; two rounds of 8 rows (16 loads each)
-            uint32_t mn[4], mx[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                u32x4 w[16];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int64_t off = base + ((int64_t)(2 * h + (i >> 2)) * ny + (i & 3)) * nx;
-                    w[2 * i] = load16_nt(vol + off);
-                    w[2 * i + 1] = load16_nt(vol + off + 8);
-                }
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint32_t ws[8] = {w[2 * i].x, w[2 * i].y, w[2 * i].z, w[2 * i].w,
-                                            w[2 * i + 1].x, w[2 * i + 1].y, w[2 * i + 1].z, w[2 * i + 1].w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
-                        mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
-                r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
-            }
-        }
-    } else if (x0 + 16 <= nx) {
-        // partial in z or y: row by row
-        if constexpr (sizeof(T) == 1) {
-            // even/odd byte lanes held as packed u16 pairs, one pair per brick
-            uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
-            for (int zz = 0; zz < zn; ++zz) {
-#pragma unroll
-                for (int yy = 0; yy < 4; ++yy) {
-                    if (yy < yn) {
-                        const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
-                        const uint4 w = load16(vol + off);
-                        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
-                            mnE[k] = pk_min16(mnE[k], e);
-                            mnO[k] = pk_min16(mnO[k], o);
-                            mxE[k] = pk_max16(mxE[k], e);
-                            mxO[k] = pk_max16(mxO[k], o);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t a = pk_min16(mnE[k], mnO[k]);
-                const uint32_t b = pk_max16(mxE[k], mxO[k]);
-                r.mn[k] = umin(lo16(a), hi16(a));
-                r.mx[k] = umax(lo16(b), hi16(b));
-            }
-        } else {
-            // u16: each 32-bit word holds 2 voxels; 2 words per brick row
-            uint32_t mn[4], mx[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
-            for (int zz = 0; zz < zn; ++zz) {
-#pragma unroll
-                for (int yy = 0; yy < 4; ++yy) {
-                    if (yy < yn) {
-                        const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
-                        const uint4 a = load16(vol + off), b = load16(vol + off + 8);
-                        const uint32_t ws[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
-                            mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
-                r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
-            }
-        }
-    } else {
-        // ragged or unaligned rows: one voxel at a time
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { r.mn[k] = 0xFFFFFFFFu; r.mx[k] = 0u; }
-        const int xn = min(16, nx - x0);
-        for (int zz = 0; zz < zn; ++zz)
-            for (int yy = 0; yy < yn; ++yy) {
-                const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int xx = 0; xx < 4; ++xx)
-                        if (4 * k + xx < xn) {
-                            const uint32_t val = vol[off + 4 * k + xx];
-                            r.mn[k] = umin(r.mn[k], val);
-                            r.mx[k] = umax(r.mx[k], val);
-                        }
-            }
+    if (x0 + 16 <= nx) {
+        if (zn == 4 && yn == 4) return quad_whole_rows<T, false>(vol, nx, ny, z0, y0, zn, yn, x0);
+        return quad_whole_rows<T, true>(vol, nx, ny, z0, y0, zn, yn, x0);
     }
+    if (nx >= 4) return quad_ragged_rows<T>(vol, nx, ny, z0, y0, zn, yn, x0);
+    // rows of fewer than 4 voxels: one voxel at a time
+    QuadMinMax<T> r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { r.mn[k] = 0xFFFFFFFFu; r.mx[k] = 0u; }
+    const int xn = min(16, nx - x0);
+    for (int zz = 0; zz < zn; ++zz)
+        for (int yy = 0; yy < yn; ++yy) {
+            const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int xx = 0; xx < 4; ++xx)
+                    if (4 * k + xx < xn) {
+                        const uint32_t val = vol[off + 4 * k + xx];
+                        r.mn[k] = umin(r.mn[k], val);
+                        r.mx[k] = umax(r.mx[k], val);
+                    }
+        }
     return r;
+}
+
+// The [min,max] of 4 bricks, one store each at any alignment (one vector
+// store: the hardware serves unaligned vector accesses, as in load16).
+template <typename T, typename P>
+__device__ __forceinline__ void store_bricks4(P mn, P mx, const QuadMinMax<T>& r) {
+    if constexpr (sizeof(T) == 1) {
+        const uint32_t a = r.mn[0] | (r.mn[1] << 8) | (r.mn[2] << 16) | (r.mn[3] << 24);
+        const uint32_t b = r.mx[0] | (r.mx[1] << 8) | (r.mx[2] << 16) | (r.mx[3] << 24);
+        __builtin_memcpy(mn, &a, 4);
+        __builtin_memcpy(mx, &b, 4);
+    } else {
+        const uint2 a = make_uint2(r.mn[0] | (r.mn[1] << 16), r.mn[2] | (r.mn[3] << 16));
+        const uint2 b = make_uint2(r.mx[0] | (r.mx[1] << 16), r.mx[2] | (r.mx[3] << 16));
+        __builtin_memcpy(mn, &a, 8);
+        __builtin_memcpy(mx, &b, 8);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -267,8 +309,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int nx, int ny, int nz,
                                                 int Bx, int By, int Bz, int Qx, T* __restrict__ bmin,
                                                 T* __restrict__ bmax, int levels,
-                                                int32_t* __restrict__ range_err,
-                                                int store_vec) {
+                                                int32_t* __restrict__ range_err) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)Qx * By * Bz;
     if (t >= total) return;
@@ -285,18 +326,8 @@ __global__ void __launch_bounds__(256) k_bricks(const T* __restrict__ vol, int n
             if (k < nb) m = umax(m, r.mx[k]);
         if (m >= (uint32_t)levels) *range_err = 1;
     }
-    if (store_vec && nb == 4) {
-        if constexpr (sizeof(T) == 1) {
-            *reinterpret_cast<uint32_t*>(bmin + base) =
-                r.mn[0] | (r.mn[1] << 8) | (r.mn[2] << 16) | (r.mn[3] << 24);
-            *reinterpret_cast<uint32_t*>(bmax + base) =
-                r.mx[0] | (r.mx[1] << 8) | (r.mx[2] << 16) | (r.mx[3] << 24);
-        } else {
-            *reinterpret_cast<uint2*>(bmin + base) =
-                make_uint2(r.mn[0] | (r.mn[1] << 16), r.mn[2] | (r.mn[3] << 16));
-            *reinterpret_cast<uint2*>(bmax + base) =
-                make_uint2(r.mx[0] | (r.mx[1] << 16), r.mx[2] | (r.mx[3] << 16));
-        }
+    if (nb == 4) {
+        store_bricks4<T>(bmin + base, bmax + base, r);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -407,8 +438,13 @@ __device__ __forceinline__ void store_u32(PDM_GLB uint8_t* p, uint32_t v) {
 template <typename DP>
 __device__ __forceinline__ void store_quad(DP __restrict__ dst, int64_t idx, int nb,
                                            uint32_t packed, bool vec) {
-    if (vec && nb == 4) {
-        store_u32(dst + idx, packed);
+    if (nb == 4) {
+        // four bytes at any alignment: one store (the hardware serves
+        // unaligned vector accesses, as for load16)
+        if (vec)
+            store_u32(dst + idx, packed);
+        else
+            __builtin_memcpy(dst + idx, &packed, 4);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -1864,9 +1900,17 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, i
                 if (k < nb) {
                     mn[k] = r.mn[k];
                     mx[k] = r.mx[k];
-                    bmin[rbase + k] = (T)r.mn[k];
-                    bmax[rbase + k] = (T)r.mx[k];
                 }
+            if (nb == 4) {
+                store_bricks4<T>(bmin + rbase, bmax + rbase, r);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < nb) {
+                        bmin[rbase + k] = (T)r.mn[k];
+                        bmax[rbase + k] = (T)r.mx[k];
+                    }
+            }
         }
         uint32_t lo = (uint32_t)bounds[0];
         for (int p = 0; p < n; ++p) {
@@ -2084,12 +2128,11 @@ hipError_t launch_bricks(const BrickArgs& a, hipStream_t s) {
     if (a.bytes == 1)
         k_bricks<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
                                              a.Bz, Qx, (uint8_t*)a.bmin, (uint8_t*)a.bmax,
-                                             a.levels, a.range_err, a.store_vec);
+                                             a.levels, a.range_err);
     else
         k_bricks<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
                                               a.By, a.Bz, Qx, (uint16_t*)a.bmin,
-                                              (uint16_t*)a.bmax, a.levels, a.range_err,
-                                              a.store_vec);
+                                              (uint16_t*)a.bmax, a.levels, a.range_err);
     return hipGetLastError();
 }
 

@@ -110,7 +110,6 @@ struct BrickArgs {
     void* bmax;
     int32_t* range_err;
     int nx, ny, nz, Bx, By, Bz, bytes, levels;
-    int store_vec;  // packed stores of 4 bricks allowed
 };
 
 struct PomArgs {
