@@ -132,10 +132,11 @@ template <typename T, bool CLAMP, typename VP>
 __device__ __forceinline__ QuadMinMax<T> quad_whole_rows(VP __restrict__ vol, int nx, int ny,
                                                          int z0, int y0, int zn, int yn, int x0) {
     QuadMinMax<T> r;
+    const int64_t base = ((int64_t)z0 * ny + y0) * nx + x0;
     auto off = [&](int i) -> int64_t {
         const int zz = CLAMP ? min(i >> 2, zn - 1) : (i >> 2);
         const int yy = CLAMP ? min(i & 3, yn - 1) : (i & 3);
-        return ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+        return base + ((int64_t)zz * ny + yy) * nx;
     };
     if constexpr (sizeof(T) == 1) {
         u32x4 w[16];
@@ -208,6 +209,7 @@ template <typename T, typename VP>
 __device__ __forceinline__ QuadMinMax<T> quad_ragged_rows(VP __restrict__ vol, int nx, int ny,
                                                           int z0, int y0, int zn, int yn, int x0) {
     QuadMinMax<T> r;
+    const int64_t base = ((int64_t)z0 * ny + y0) * nx;
     int pos[4];
     uint32_t mlo[4], mhi[4];  // voxels of the brick before: bits set in the loaded words
 #pragma unroll
@@ -219,39 +221,113 @@ __device__ __forceinline__ QuadMinMax<T> quad_ragged_rows(VP __restrict__ vol, i
         mlo[k] = (uint32_t)m;
         mhi[k] = (uint32_t)(m >> 32);
     }
-    uint32_t mnA[4], mnB[4], mxA[4], mxB[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { mnA[k] = mnB[k] = 0xFFFFFFFFu; mxA[k] = mxB[k] = 0u; }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t row = ((int64_t)(z0 + min(i >> 2, zn - 1)) * ny + (y0 + min(i & 3, yn - 1))) * nx;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if constexpr (sizeof(T) == 1) {
-                const uint32_t w = load4(vol + row + pos[k]);
-                const uint32_t lo = w | mlo[k], hi = w & ~mlo[k];
-                mnA[k] = pk_min16(mnA[k], even_bytes(lo));
-                mnB[k] = pk_min16(mnB[k], odd_bytes(lo));
-                mxA[k] = pk_max16(mxA[k], even_bytes(hi));
-                mxB[k] = pk_max16(mxB[k], odd_bytes(hi));
-            } else {
-                const uint2 w = load8(vol + row + pos[k]);
-                mnA[k] = pk_min16(mnA[k], pk_min16(w.x | mlo[k], w.y | mhi[k]));
-                mxA[k] = pk_max16(mxA[k], pk_max16(w.x & ~mlo[k], w.y & ~mhi[k]));
-            }
-        }
-    }
+    // one brick (its 16 row loads in flight) at a time: few registers, so the
+    // callers keep the occupancy their whole-quad path sets
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t a = pk_min16(mnA[k], mnB[k]);
-        const uint32_t b = pk_max16(mxA[k], mxB[k]);
+        uint32_t mnA = 0xFFFFFFFFu, mnB = 0xFFFFFFFFu, mxA = 0u, mxB = 0u;
+        typename std::conditional<sizeof(T) == 1, uint32_t, uint2>::type w[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t row = base + ((int64_t)min(i >> 2, zn - 1) * ny + min(i & 3, yn - 1)) * nx;
+            if constexpr (sizeof(T) == 1)
+                w[i] = load4(vol + row + pos[k]);
+            else
+                w[i] = load8(vol + row + pos[k]);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if constexpr (sizeof(T) == 1) {
+                const uint32_t lo = w[i] | mlo[k], hi = w[i] & ~mlo[k];
+                mnA = pk_min16(mnA, even_bytes(lo));
+                mnB = pk_min16(mnB, odd_bytes(lo));
+                mxA = pk_max16(mxA, even_bytes(hi));
+                mxB = pk_max16(mxB, odd_bytes(hi));
+            } else {
+                mnA = pk_min16(mnA, pk_min16(w[i].x | mlo[k], w[i].y | mhi[k]));
+                mxA = pk_max16(mxA, pk_max16(w[i].x & ~mlo[k], w[i].y & ~mhi[k]));
+            }
+        }
+        const uint32_t a = pk_min16(mnA, mnB);
+        const uint32_t b = pk_max16(mxA, mxB);
         r.mn[k] = umin(lo16(a), hi16(a));
         r.mx[k] = umax(lo16(b), hi16(b));
+        __builtin_amdgcn_sched_barrier(0);  // the next brick's loads stay below
     }
     return r;
 }
 
+// The quad's rows one at a time (a brick layer cut in z or y): few registers.
 template <typename T, typename VP>
+__device__ __forceinline__ QuadMinMax<T> quad_rows_looped(VP __restrict__ vol, int nx, int ny,
+                                                          int z0, int y0, int zn, int yn, int x0) {
+    QuadMinMax<T> r;
+    if constexpr (sizeof(T) == 1) {
+        // even/odd byte lanes held as packed u16 pairs, one pair per brick
+        uint32_t mnE[4], mnO[4], mxE[4], mxO[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { mnE[k] = mnO[k] = 0xFFFFFFFFu; mxE[k] = mxO[k] = 0u; }
+        for (int zz = 0; zz < zn; ++zz) {
+#pragma unroll
+            for (int yy = 0; yy < 4; ++yy) {
+                if (yy < yn) {
+                    const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+                    const uint4 w = load16(vol + off);
+                    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t e = even_bytes(ws[k]), o = odd_bytes(ws[k]);
+                        mnE[k] = pk_min16(mnE[k], e);
+                        mnO[k] = pk_min16(mnO[k], o);
+                        mxE[k] = pk_max16(mxE[k], e);
+                        mxO[k] = pk_max16(mxO[k], o);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t a = pk_min16(mnE[k], mnO[k]);
+            const uint32_t b = pk_max16(mxE[k], mxO[k]);
+            r.mn[k] = umin(lo16(a), hi16(a));
+            r.mx[k] = umax(lo16(b), hi16(b));
+        }
+    } else {
+        // u16: each 32-bit word holds 2 voxels; 2 words per brick row
+        uint32_t mn[4], mx[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { mn[k] = 0xFFFFFFFFu; mx[k] = 0u; }
+        for (int zz = 0; zz < zn; ++zz) {
+#pragma unroll
+            for (int yy = 0; yy < 4; ++yy) {
+                if (yy < yn) {
+                    const int64_t off = ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + x0;
+                    const uint4 a = load16(vol + off), b = load16(vol + off + 8);
+                    const uint32_t ws[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        mn[k] = pk_min16(mn[k], pk_min16(ws[2 * k], ws[2 * k + 1]));
+                        mx[k] = pk_max16(mx[k], pk_max16(ws[2 * k], ws[2 * k + 1]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r.mn[k] = umin(lo16(mn[k]), hi16(mn[k]));
+            r.mx[k] = umax(lo16(mx[k]), hi16(mx[k]));
+        }
+    }
+    return r;
+}
+
+// Brick [min,max] of the quad.  FAST_EDGES: quads at the volume's edges (a
+// brick layer cut in z or y, 16 voxels that run past the row end) take the
+// unrolled paths above; otherwise compact looped ones, for a caller whose
+// register budget must stay that of the whole-quad path (with the unrolled
+// edge paths inlined, the compiler schedules the plain x pass for 190
+// registers instead of 97, which halves its occupancy on whole rows).
+template <typename T, bool FAST_EDGES = true, typename VP>
 __device__ __forceinline__ QuadMinMax<T> quad_minmax(VP __restrict__ vol, int nx, int ny, int nz,
                                                      int q, int by, int bz) {
     const int x0 = 16 * q;
@@ -259,10 +335,16 @@ __device__ __forceinline__ QuadMinMax<T> quad_minmax(VP __restrict__ vol, int nx
     const int zn = min(4, nz - z0), yn = min(4, ny - y0);
     if (x0 + 16 <= nx) {
         if (zn == 4 && yn == 4) return quad_whole_rows<T, false>(vol, nx, ny, z0, y0, zn, yn, x0);
-        return quad_whole_rows<T, true>(vol, nx, ny, z0, y0, zn, yn, x0);
+        if constexpr (FAST_EDGES)
+            return quad_whole_rows<T, true>(vol, nx, ny, z0, y0, zn, yn, x0);
+        else
+            return quad_rows_looped<T>(vol, nx, ny, z0, y0, zn, yn, x0);
     }
-    if (nx >= 4) return quad_ragged_rows<T>(vol, nx, ny, z0, y0, zn, yn, x0);
-    // rows of fewer than 4 voxels: one voxel at a time
+    if constexpr (FAST_EDGES) {
+        if (nx >= 4) return quad_ragged_rows<T>(vol, nx, ny, z0, y0, zn, yn, x0);
+    }
+    // one voxel at a time (rows of fewer than 4 voxels; or ragged rows when
+    // not FAST_EDGES)
     QuadMinMax<T> r;
 #pragma unroll
     for (int k = 0; k < 4; ++k) { r.mn[k] = 0xFFFFFFFFu; r.mx[k] = 0u; }
@@ -574,7 +656,7 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
     // the first segment's voxels are requested before the bitmap set-up, so
     // the loads are in flight while the block fills LDS
     QuadMinMax<T> r0;
-    if (live && 4 * lane < Bx) r0 = quad_minmax<T>(vol, nx, ny, nz, lane, by, bz);
+    if (live && 4 * lane < Bx) r0 = quad_minmax<T, false>(vol, nx, ny, nz, lane, by, bz);
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) s_words[i] = bits.w[i];
     for (int i = threadIdx.x; i <= nwords; i += blockDim.x) s_pre[i] = bits.pre[i];
     __syncthreads();
@@ -588,7 +670,7 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
         const int q = s * kWave + lane;  // quad index within the row
         uint32_t o = 0;
         if (4 * q < Bx) {
-            const QuadMinMax<T> r = s == 0 ? r0 : quad_minmax<T>(vol, nx, ny, nz, q, by, bz);
+            const QuadMinMax<T> r = s == 0 ? r0 : quad_minmax<T, false>(vol, nx, ny, nz, q, by, bz);
             const int nb = min(4, Bx - 4 * q);
             for (int k = 0; k < 4; ++k)
                 if (k < nb && any_bit(s_words, s_pre, umin(r.mn[k], top), umin(r.mx[k], top)))
