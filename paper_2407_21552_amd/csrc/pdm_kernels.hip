@@ -15,10 +15,17 @@
 //   k_pom_x         [min,max] -> for every partition, the POM and the distance
 //                   to the nearest occupied brick along x (wave ballots).
 //   k_plain_x       volume + TF -> occupancy and x distance (plain method).
-//   k_dist_axis     x distances -> full chessboard distances: 1-D max-min pass
-//                   along y or z, one lane per line, linear-time scan, lines
-//                   staged in LDS (few lines: one map).
-//   k_dist_global   the same pass on global memory (many lines: all maps).
+//   k_plain_cached_x cached [min,max] + TF -> occupancy and x distance (the
+//                   plain method without reading the volume).
+//   k_dist_lines    x distances -> full chessboard distances: 1-D max-min
+//                   pass along y or z, one lane per line, linear-time scan,
+//                   the line in registers (many lines: all maps of a grid).
+//   k_dist_pairs    the same pass with two lanes per line (forward and
+//                   backward halves at once; few lines: one map).
+//   k_dist_global   the same pass on global memory (lines over 256 bricks,
+//                   or offsets past 31 bits).
+//   k_dist_axis, k_dist_split  the same pass with lines staged in LDS (lines
+//                   of at most 16 bricks).
 //   k_combine       min over a list of G-byte maps (the active PDMs, or the
 //                   range-table maps covering them), 16 bytes per lane.
 //   k_range_level   one level of the range table: min of two maps.
