@@ -30,7 +30,8 @@ def test_traffic_record_parses_and_is_tied_to_the_source(tmp_path, monkeypatch):
     rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     cal = rec["calibration"]
     assert cal["read_factor"] > 0 and cal["write_factor"] > 0
-    for name in ("k_plain_x", "k_combine", "k_bricks", "k_pom_x", "k_dist_lines"):
+    for name in ("k_plain_x", "k_combine", "k_bricks", "k_pom_x", "k_dist_lines<false>",
+                 "k_dist_lines<true>"):
         k = rec["kernels"][name]
         assert k["hbm_bytes_per_launch"] > 0 and k["launches"] >= 1
     # a record is used only for the source it was taken on

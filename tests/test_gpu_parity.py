@@ -176,6 +176,9 @@ MANY_LINE_SHAPES = [
     ((160, 1024, 132), np.uint16, 4096, 256, "40x256x33 grid: 256-brick y lines, u16"),
     ((68, 66, 4000), np.uint8, 256, 32, "17x17x1000 grid: lines of 17 (one full chunk + 1)"),
     ((80, 1020, 256), np.uint8, 256, 256, "20x255x64 grid: 255-brick y lines, 256 partitions"),
+    # the longest lines whose values are clamped to the line length (a table
+    # of 255 rows); z lines of 20, most of them with every value above 20
+    ((80, 1016, 256), np.uint8, 256, 256, "20x254x64 grid: 254-brick y lines, clamped"),
     ((8, 400, 1024), np.uint8, 256, 64, "2x100x256 grid: 2-brick z lines"),
 ]
 

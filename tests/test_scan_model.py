@@ -13,7 +13,9 @@ last[f(i)] = i, sets F(i) = min(f(i), min(v+1, max(v, i-W))) and reads
 W = last[F(i)].  The split variant runs the forward and backward passes at once on two lanes, each
 first over its half of the line and then over the half the other has done,
 with values clamped at min(m, 255) and the line's minimum as the result
-wherever every value is at least that clamp.  These models mirror that logic
+wherever every value is at least that clamp; the one-lane register kernel
+clamps the same way, so its table needs only min(m, 255) + 1 rows.  These
+models mirror that logic
 so a change to it can be checked here first."""
 import numpy as np
 import pytest
@@ -170,20 +172,28 @@ def _padded_words(f, nch):
 
 def registers_one_lane(f):
     """The one-lane register kernel: the line padded to whole chunks of 16,
-    a forward pass from a start state above every value, then a backward
-    pass from the padded end (positions counted from it), stores of padded
-    positions sent to the last position before its own store."""
+    a forward pass from a start state above every value over the values
+    clamped at s = min(m, 255) (a table of s + 1 rows; the line's minimum
+    kept on the side), then a backward pass from the padded end (positions
+    counted from it) whose stores take max(result, fix), fix being the
+    line's minimum when every value is at least s and 0 otherwise; stores of
+    padded positions go to the last position before its own store."""
     m = len(f)
     nch = -(-m // 16)
     pend = 16 * nch - 1
+    s = min(m, 255)
     w = _padded_words(f, nch)
-    fwd = Lane(256, 511)
+    fwd = Lane(s + 1, 511)
+    lmin = 255
     for p in range(pend + 1):
-        w[p // 4][p % 4] = fwd.step(p, w[p // 4][p % 4])
-    bwd = Lane(256, 511)
+        raw = w[p // 4][p % 4]
+        lmin = min(lmin, raw)
+        w[p // 4][p % 4] = fwd.step(p, min(raw, s))
+    fix = lmin if lmin >= s else 0
+    bwd = Lane(s + 1, 511)
     out = [None] * m
     for p in range(pend, -1, -1):
-        out[min(p, m - 1)] = bwd.step(pend - p, w[p // 4][p % 4])
+        out[min(p, m - 1)] = max(bwd.step(pend - p, w[p // 4][p % 4]), fix)
     return np.array(out)
 
 
