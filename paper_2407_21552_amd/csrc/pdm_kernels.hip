@@ -1213,20 +1213,20 @@ __host__ __device__ constexpr int scan_table_bytes(int m) { return (scan_rows(m)
 
 // The two-sided pass of one line per lane, the line in registers: lane's
 // line at byte offsets voff + p * stride (p < m <= 256) from `base`, all
-// offsets below 2^31.  `tbl` holds scan_table_bytes(m) bytes (with CLAMP;
-// else scan_table_bytes(255)).  Called by the
-// whole wave; returns early (all lanes) when every byte of the wave's lines
-// is 255.
+// offsets below 2^31.  `tbl` holds scan_table_bytes(m) bytes with CLAMP,
+// else scan_table_bytes(255).  Called by the whole wave; returns early (all
+// lanes) when every byte of the wave's lines is 255.
 //
 // With CLAMP, values are clamped at s = min(m, 255) on the way in, so the
 // table needs s + 1 rows, not 256, and more waves fit a compute unit on short
-// lines (without it the table has all 256 rows).  Two
+// lines (without it the table has all 256 rows).  For m < 255 (s = m): two
 // positions of one line are less than m apart, so a term max(|i-j|, f(j))
-// with f(j) >= s is f(j) >= s, while every term with f(j) < s is below s:
-// where the line holds a value below s, the clamped result is below s and
+// with f(j) >= s is f(j), while every term with f(j) < s is below s.  Where
+// the line holds a value below s, the clamped result is therefore below s and
 // exact; where every value is at least s, the result is the line's minimum
 // everywhere (and the clamped pass gives s).  The backward pass's stores take
 // max(result, fix) with fix = that minimum on such lines, 0 on the others.
+// For m >= 255 (s = 255) the clamp changes no value.
 template <bool CLAMP>
 __device__ __forceinline__ void scan_lines_regs(uint8_t* base, int voff, int stride, int m,
                                                 uint8_t* __restrict__ tbl_mem) {
