@@ -117,6 +117,45 @@ def test_odd_shapes(pdm, orc, shape, dtype, levels, n, label):
     run_all(pdm, orc, vol, levels, bounds, tfs(levels, 6, sum(shape)), label)
 
 
+def random_case(seed):
+    """One seeded random case: shape, intensity type and levels, partition
+    borders at random cut points, a piecewise-constant volume with noise."""
+    rng = np.random.default_rng(10_000 + seed)
+    kind = seed % 4
+    spans = [(1, 9), (10, 70), (60, 300)]
+    while True:
+        shape = tuple(int(rng.integers(*spans[int(rng.integers(0, 3))])) for _ in range(3))
+        if np.prod(shape) <= 2_500_000:
+            break
+    if kind in (0, 1):
+        dtype, levels = np.uint8, int(rng.choice([256, 256, 100, 17]))
+    else:
+        dtype, levels = np.uint16, int(rng.choice([4096, 1000, 16384, 60000]))
+    n = int(rng.integers(1, min(levels, 256) + 1))
+    cuts = np.sort(rng.choice(np.arange(1, levels), size=n - 1, replace=False)) if n > 1 else []
+    bounds = np.concatenate([[0], cuts, [levels]]).astype(np.int32)
+    vol = blocky(shape, dtype, levels, seed=seed, keep=float(rng.uniform(0.02, 0.6)),
+                 cell=int(rng.integers(1, 7)))
+    noise = rng.integers(0, levels, size=shape)
+    vol = np.where(rng.random(shape) < rng.uniform(0.0, 0.05), noise, vol).astype(dtype)
+    return vol, levels, bounds
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_cases(pdm, orc, seed):
+    """Seeded random shapes (1 to 300 voxels per axis), intensity types and
+    level counts (u16 above 16384 levels: D' only), partitions at random
+    borders (1 to 256 of them), volumes of random density and granularity:
+    bricks, every PDM, and D', D and D from the cached ranges for three
+    random TFs plus the empty, all-opaque and special-value TFs; the same in
+    the EXACT reading where its level limit allows."""
+    vol, levels, bounds = random_case(seed)
+    alphas = tfs(levels, 3, 500 + seed)
+    run_all(pdm, orc, vol, levels, bounds, alphas, f"random case {seed}")
+    if levels <= 16384:
+        run_exact(pdm, orc, vol, levels, bounds, alphas, f"random case {seed}")
+
+
 def test_capped_lines_closed_form(pdm, orc):
     """A single occupied brick at one end of 1x1xN and Nx1x1 grids: the
     distance along the line is min(k, 255)."""
