@@ -541,6 +541,23 @@ __device__ __forceinline__ void store_quad(DP __restrict__ dst, int64_t idx, int
     }
 }
 
+// The smallest brick minimum and the largest brick maximum over the wave's
+// lanes (wave-uniform; lanes without bricks hold min = ~0, max = 0).  A
+// partition [lo, hi] with hi < wmin or lo > wmax holds none of the wave's
+// bricks, so every distance of its rows is the cap and no x pass is needed.
+__device__ __forceinline__ void wave_value_range(const uint32_t (&mn)[4], const uint32_t (&mx)[4],
+                                                 uint32_t& wmin, uint32_t& wmax) {
+    uint32_t a = umin(umin(mn[0], mn[1]), umin(mn[2], mn[3]));
+    uint32_t b = umax(umax(mx[0], mx[1]), umax(mx[2], mx[3]));
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        a = umin(a, (uint32_t)__shfl_xor((int)a, o, kWave));
+        b = umax(b, (uint32_t)__shfl_xor((int)b, o, kWave));
+    }
+    wmin = __builtin_amdgcn_readfirstlane(a);
+    wmax = __builtin_amdgcn_readfirstlane(b);
+}
+
 // ---------------------------------------------------------------------------
 // k_pom_x: one wave per brick row (bz, by); 4 waves per work-group.  For
 // every partition p: POM nibble from [min,max] (RANGE reading) and the x
@@ -568,12 +585,17 @@ __global__ void __launch_bounds__(256) k_pom_x(const T* __restrict__ bmin,
             mn[k] = k < nb ? (uint32_t)bmin[rbase + k] : 0xFFFFFFFFu;
             mx[k] = k < nb ? (uint32_t)bmax[rbase + k] : 0u;
         }
+        uint32_t wmin, wmax;
+        wave_value_range(mn, mx, wmin, wmax);
         for (int p = 0; p < n; ++p) {
             const uint32_t lo = (uint32_t)bounds.b[p], hi = (uint32_t)bounds.b[p + 1] - 1u;
-            uint32_t o = 0;
+            uint32_t packed = 0xFFFFFFFFu;
+            if (hi >= wmin && lo <= wmax) {
+                uint32_t o = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
-            const uint32_t packed = x_distances_rows(o, lane, W);
+                for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+                packed = x_distances_rows(o, lane, W);
+            }
             if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase, nb, packed, store_vec);
         }
         return;
@@ -590,12 +612,17 @@ __global__ void __launch_bounds__(256) k_pom_x(const T* __restrict__ bmin,
             mn[k] = k < nb ? (uint32_t)bmin[rbase + 4 * lane + k] : 0xFFFFFFFFu;
             mx[k] = k < nb ? (uint32_t)bmax[rbase + 4 * lane + k] : 0u;
         }
+        uint32_t wmin, wmax;
+        wave_value_range(mn, mx, wmin, wmax);
         for (int p = 0; p < n; ++p) {
             const uint32_t lo = (uint32_t)bounds.b[p], hi = (uint32_t)bounds.b[p + 1] - 1u;
-            uint32_t o = 0;
+            uint32_t packed = 0xFFFFFFFFu;
+            if (hi >= wmin && lo <= wmax) {
+                uint32_t o = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
-            const uint32_t packed = x_distances(o, lane, 0, -kNone, kNone);
+                for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+                packed = x_distances(o, lane, 0, -kNone, kNone);
+            }
             if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase + 4 * lane, nb, packed, store_vec);
         }
         return;
@@ -2050,13 +2077,18 @@ __device__ __forceinline__ void batch_rows(const BatchVol& d, int bz, int by0, i
                     }
             }
         }
+        uint32_t wmin, wmax;
+        wave_value_range(mn, mx, wmin, wmax);
         uint32_t lo = (uint32_t)bounds[0];
         for (int p = 0; p < n; ++p) {
             const uint32_t next = (uint32_t)bounds[p + 1], hi = next - 1u;
-            uint32_t o = 0;
+            uint32_t packed = 0xFFFFFFFFu;
+            if (hi >= wmin && lo <= wmax) {
+                uint32_t o = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
-            const uint32_t packed = x_distances_rows(o, lane, W);
+                for (int k = 0; k < 4; ++k) o |= (mn[k] <= hi && mx[k] >= lo) ? (1u << k) : 0u;
+                packed = x_distances_rows(o, lane, W);
+            }
             if (nb > 0) store_quad(pdms + (int64_t)p * G, rbase, nb, packed, vec);
             lo = next;
         }
@@ -2171,7 +2203,7 @@ __device__ __forceinline__ bool grid_barrier(BatchSync* st, uint32_t k, uint64_t
     return ok;
 }
 
-__global__ void __launch_bounds__(kWave) k_batch_single(const BatchVol* __restrict__ vols, int count,
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) k_batch_single(const BatchVol* __restrict__ vols, int count,
                                                         int64_t total0, int64_t total1,
                                                         int64_t total2, int lines_mult,
                                                         BatchSync* st, uint64_t limit_ticks) {
