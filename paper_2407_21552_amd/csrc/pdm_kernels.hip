@@ -2203,7 +2203,7 @@ __device__ __forceinline__ bool grid_barrier(BatchSync* st, uint32_t k, uint64_t
     return ok;
 }
 
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) k_batch_single(const BatchVol* __restrict__ vols, int count,
+__global__ void __launch_bounds__(kWave) k_batch_single(const BatchVol* __restrict__ vols, int count,
                                                         int64_t total0, int64_t total1,
                                                         int64_t total2, int lines_mult,
                                                         BatchSync* st, uint64_t limit_ticks) {
