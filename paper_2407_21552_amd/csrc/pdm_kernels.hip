@@ -19,7 +19,9 @@
 //                   plain method without reading the volume).
 //   k_dist_lines    x distances -> full chessboard distances: 1-D max-min
 //                   pass along y or z, one lane per line, linear-time scan,
-//                   the line in registers (many lines: all maps of a grid).
+//                   the line in registers (many lines: all maps of a grid);
+//                   on lines under 255 bricks the values are clamped to the
+//                   line length and the table sized to it.
 //   k_dist_pairs    the same pass with two lanes per line (forward and
 //                   backward halves at once; few lines: one map).
 //   k_dist_global   the same pass on global memory (lines over 256 bricks,
@@ -1676,7 +1678,7 @@ __global__ void __launch_bounds__(kScanLanes) k_dist_split(uint8_t* __restrict__
 }
 
 // The scan on global memory directly, one lane per line, 64 lanes per
-// work-group and only the table in LDS (17.5 KB with 8-bit entries), so up to
+// work-group and only the table in LDS (17.4 KB with 8-bit entries), so up to
 // nine waves share a compute unit: the choice when the passes cover many
 // lines (all partitions at once) and occupancy hides the memory latency.
 // P = uint16_t serves lines longer than 256 bricks (positions beyond 255).
