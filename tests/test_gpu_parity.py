@@ -156,6 +156,48 @@ def test_random_cases(pdm, orc, seed):
         run_exact(pdm, orc, vol, levels, bounds, alphas, f"random case {seed}")
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches(pdm, orc, seed):
+    """Seeded random batches of 3 to 12 volumes (random shapes up to 200
+    voxels per axis, u8 and u16 with random level counts, 1 to 255
+    partitions at random borders) built in one batched build with random
+    launch knobs (grouped or single launch, alternating), then updated in one
+    batched TF update: bricks, every PDM and every D' against the oracle."""
+    import torch
+    rng = np.random.default_rng(20_000 + seed)
+    count = int(rng.integers(3, 13))
+    vols, items, wants = [], [], []
+    for k in range(count):
+        vol, levels, bounds = random_case(100 * seed + k)
+        vol = np.ascontiguousarray(vol[:200, :200, :200])  # at most 50 bricks per axis
+        v = pdm.Volume(pdm.to_device(vol), levels, bounds, voxel_dtype=vol.dtype)
+        vols.append((vol, v, bounds, levels))
+        items.append((v.desc, v.volume, v.bmin, v.bmax, bounds, v.pdms))
+    config = dict(rows_per_item=int(rng.choice([1, 2, 4])), lines_mult=int(rng.choice([1, 2, 4])),
+                  largest_first=int(rng.integers(0, 2)), single_launch=seed % 2)
+    ws = torch.empty(pdm.batch_workspace_bytes(count), dtype=torch.uint8, device="cuda")
+    say(f"[case] random batch {seed}: {count} volumes, config {config}")
+    pdm.batch_build(items, ws, config)
+    torch.cuda.synchronize()
+    assert pdm.batch_error(ws) == 0
+    upd = []
+    for k, (vol, v, bounds, levels) in enumerate(vols):
+        bmin, bmax = orc.bricks(vol)
+        np.testing.assert_array_equal(pdm.from_device(v.bmin, vol.dtype), bmin, err_msg=f"bmin {k}")
+        np.testing.assert_array_equal(pdm.from_device(v.bmax, vol.dtype), bmax, err_msg=f"bmax {k}")
+        want = orc.pdms(vol, bounds, levels, brick_minmax=(bmin, bmax))
+        np.testing.assert_array_equal(pdm.from_device(v.pdms), want, err_msg=f"pdms {k}")
+        alpha = W.trapezoid_tf(levels, int(rng.integers(1, 5)), rng)
+        out = torch.empty(v.G, dtype=torch.uint8, device="cuda")
+        upd.append((v.desc, v.pdms, bounds, alpha, out))
+        wants.append(orc.tf_update(want, bounds, alpha, levels))
+    masks = pdm.batch_tf_update(upd)
+    torch.cuda.synchronize()
+    for k, ((dp, m), it) in enumerate(zip(wants, upd)):
+        np.testing.assert_array_equal(masks[k], m, err_msg=f"mask {k}")
+        np.testing.assert_array_equal(pdm.from_device(it[4]).reshape(dp.shape), dp, err_msg=f"D' {k}")
+
+
 def test_capped_lines_closed_form(pdm, orc):
     """A single occupied brick at one end of 1x1xN and Nx1x1 grids: the
     distance along the line is min(k, 255)."""
