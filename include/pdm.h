@@ -58,7 +58,9 @@ extern "C" {
 #define PDM_BRICK 4             /* block size b = 4 (Sec. 3.1) */
 #define PDM_MAX_GRID_AXIS 65535 /* bricks per axis */
 #define PDM_MAX_GRID_X 16384    /* bricks along x */
-#define PDM_MAX_PLAIN_LEVELS 16384 /* levels accepted by the plain method */
+#define PDM_MAX_PLAIN_LEVELS 65536 /* levels accepted by the plain method (any u16 range) */
+#define PDM_MAX_PLAIN_BITMAP_LEVELS 16384 /* above this, the non-zero opacity levels go as runs */
+#define PDM_MAX_PLAIN_RUNS 512     /* runs of non-zero opacity accepted above 16384 levels */
 #define PDM_MAX_EXACT_LEVELS 16384 /* levels accepted by the EXACT calls */
 #define PDM_MAX_EXACT_GRID_X 256   /* bricks along x accepted by the EXACT build */
 
@@ -172,7 +174,10 @@ pdm_status pdm_tf_update_ranges(const pdm_volume* v, const uint8_t* d_pdms, cons
  * every brick under the TF (occupied when some intensity i in the brick's
  * [min, max] has h_alpha[i] != 0, tested as in pdm_active_set) and its
  * clamped chessboard distance map D.
- * h_alpha: v->levels floats, levels <= PDM_MAX_PLAIN_LEVELS.  d_dist: G bytes.
+ * h_alpha: v->levels floats, levels <= PDM_MAX_PLAIN_LEVELS.  Up to
+ * PDM_MAX_PLAIN_BITMAP_LEVELS levels any table is accepted; above, the
+ * levels with h_alpha != 0 must form at most PDM_MAX_PLAIN_RUNS maximal runs
+ * (a TF of a few ramps forms a few), else PDM_E_UNSUPPORTED.  d_dist: G bytes.
  * Equivalent to pdm_plain_distance_x followed by pdm_distance_yz(count = 1).
  * Voxels >= levels are a precondition violation (see pdm_build_bricks). */
 pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const float* h_alpha,
@@ -185,8 +190,8 @@ pdm_status pdm_full_recompute(const pdm_volume* v, const void* d_volume, const f
  * an implementation of the plain method (Sec. 2, Sec. 4.2) keeping the
  * brick ranges of the one-time initialisation would run per TF change.
  * d_bmin/d_bmax: output of pdm_build_bricks (G elements of v->dtype each).
- * levels <= PDM_MAX_PLAIN_LEVELS.  d_dist: G bytes.  Equivalent to
- * pdm_plain_cached_distance_x followed by pdm_distance_yz(count = 1). */
+ * levels and h_alpha as for pdm_full_recompute.  d_dist: G bytes.  Equivalent
+ * to pdm_plain_cached_distance_x followed by pdm_distance_yz(count = 1). */
 pdm_status pdm_full_recompute_cached(const pdm_volume* v, const void* d_bmin, const void* d_bmax,
                                      const float* h_alpha, uint8_t* d_dist, hipStream_t stream);
 
@@ -315,7 +320,7 @@ pdm_status pdm_build_partitions_exact(const pdm_volume* v, const void* d_volume,
 
 /* Plain method in the EXACT reading: D from the volume, a brick being
  * occupied when one of its voxels has h_alpha[voxel] != 0.
- * levels <= PDM_MAX_PLAIN_LEVELS.  Equivalent to pdm_plain_exact_distance_x +
+ * levels <= PDM_MAX_EXACT_LEVELS.  Equivalent to pdm_plain_exact_distance_x +
  * pdm_distance_yz(count = 1). */
 pdm_status pdm_full_recompute_exact(const pdm_volume* v, const void* d_volume,
                                     const float* h_alpha, uint8_t* d_dist, hipStream_t stream);

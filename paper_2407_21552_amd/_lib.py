@@ -24,6 +24,8 @@ PDM_U8, PDM_U16 = 1, 2
 BRICK = 4
 DIST_CAP = 255
 MAX_PARTITIONS = 256
+MAX_PLAIN_BITMAP_LEVELS = 16384  # above: the non-zero opacity levels go as runs
+MAX_PLAIN_RUNS = 512             # runs accepted above MAX_PLAIN_BITMAP_LEVELS levels
 
 
 class PdmError(RuntimeError):

@@ -68,26 +68,48 @@ void active_mask(const int32_t* b, int32_t n, const float* alpha, uint64_t mask[
 pdm_status from_hip(hipError_t e) { return e == hipSuccess ? PDM_OK : PDM_E_DEVICE; }
 
 // Validation and kernel arguments shared by both readings of the plain
-// method: the non-zero opacity bitmap and the volume geometry.
+// method: the non-zero opacity levels and the volume geometry.  Up to
+// PDM_MAX_PLAIN_BITMAP_LEVELS levels they go as a bitmap with per-word prefix
+// counts; above, when `allow_runs`, as the maximal runs of non-zero levels
+// (at most PDM_MAX_PLAIN_RUNS of them).
 pdm_status plain_args(const pdm_volume* v, const void* d_volume, const float* h_alpha,
-                      uint8_t* d_dist, pdm::PlainArgs* a, AlphaBits* bits) {
+                      uint8_t* d_dist, pdm::PlainArgs* a, AlphaBits* bits, bool allow_runs) {
     pdm_grid g;
     const pdm_status st = check_volume(v, &g);
     if (st != PDM_OK) return st;
     if (d_volume == nullptr || h_alpha == nullptr || d_dist == nullptr) return PDM_E_INVAL;
-    if (v->levels > PDM_MAX_PLAIN_LEVELS) return PDM_E_UNSUPPORTED;
+    static_assert(PDM_MAX_PLAIN_BITMAP_LEVELS == 32 * PDM_ALPHA_WORDS, "bitmap size");
+    static_assert(PDM_MAX_PLAIN_RUNS <= PDM_ALPHA_WORDS, "run list size");
+    const bool runs = v->levels > PDM_MAX_PLAIN_BITMAP_LEVELS;
+    if (v->levels > PDM_MAX_PLAIN_LEVELS || (runs && !allow_runs)) return PDM_E_UNSUPPORTED;
     memset(bits, 0, sizeof(*bits));
     const opacity_bits* u = reinterpret_cast<const opacity_bits*>(h_alpha);
-    for (int32_t i = 0; i < v->levels; ++i)
-        if (u[i] & kMagnitude) bits->w[i >> 5] |= 1u << (i & 31);
-    // prefix counts of set bits per word: any set bit in [lo, hi] is O(1)
-    const int32_t nwords = (v->levels + 31) / 32;
-    uint32_t acc = 0;
-    for (int32_t i = 0; i < nwords; ++i) {
-        bits->pre[i] = (uint16_t)acc;
-        acc += (uint32_t)__builtin_popcount(bits->w[i]);
+    int32_t count = 0;
+    if (runs) {
+        // levels < 65536, so a run's first and last level take 16 bits each
+        for (int32_t i = 0; i < v->levels;) {
+            if (!(u[i] & kMagnitude)) {
+                ++i;
+                continue;
+            }
+            int32_t j = i;
+            while (j + 1 < v->levels && (u[j + 1] & kMagnitude)) ++j;
+            if (count == PDM_MAX_PLAIN_RUNS) return PDM_E_UNSUPPORTED;
+            bits->w[count++] = (uint32_t)i | ((uint32_t)j << 16);
+            i = j + 1;
+        }
+    } else {
+        for (int32_t i = 0; i < v->levels; ++i)
+            if (u[i] & kMagnitude) bits->w[i >> 5] |= 1u << (i & 31);
+        // prefix counts of set bits per word: any set bit in [lo, hi] is O(1)
+        count = (v->levels + 31) / 32;
+        uint32_t acc = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            bits->pre[i] = (uint16_t)acc;
+            acc += (uint32_t)__builtin_popcount(bits->w[i]);
+        }
+        bits->pre[count] = (uint16_t)acc;
     }
-    bits->pre[nwords] = (uint16_t)acc;
     a->vol = d_volume;
     a->dist = d_dist;
     a->nx = v->nx;
@@ -97,9 +119,10 @@ pdm_status plain_args(const pdm_volume* v, const void* d_volume, const float* h_
     a->By = g.by;
     a->Bz = g.bz;
     a->bytes = v->dtype;
-    a->nwords = (v->levels + 31) / 32;
+    a->nwords = count;
     a->levels = v->levels;
     a->store_vec = g.bx % 4 == 0 && aligned(d_dist, 4);
+    a->runs = runs ? 1 : 0;
     return PDM_OK;
 }
 
@@ -550,7 +573,7 @@ pdm_status pdm_plain_distance_x(const pdm_volume* v, const void* d_volume, const
                                 uint8_t* d_dist, hipStream_t stream) {
     pdm::PlainArgs a;
     AlphaBits bits;
-    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits);
+    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits, true);
     if (st != PDM_OK) return st;
     return from_hip(pdm::launch_plain_x(a, bits, stream));
 }
@@ -569,7 +592,7 @@ pdm_status pdm_plain_cached_distance_x(const pdm_volume* v, const void* d_bmin, 
     AlphaBits bits;
     // the bitmap and the geometry as for the plain method (d_bmin stands in
     // for the volume pointer in the shared checks)
-    const pdm_status st = plain_args(v, d_bmin, h_alpha, d_dist, &pa, &bits);
+    const pdm_status st = plain_args(v, d_bmin, h_alpha, d_dist, &pa, &bits, true);
     if (st != PDM_OK) return st;
     pdm::CachedArgs a;
     a.bmin = d_bmin;
@@ -582,6 +605,7 @@ pdm_status pdm_plain_cached_distance_x(const pdm_volume* v, const void* d_bmin, 
     a.nwords = pa.nwords;
     a.levels = pa.levels;
     a.store_vec = pa.store_vec;
+    a.runs = pa.runs;
     a.load_vec = pa.Bx % 4 == 0 && aligned(d_bmin, 4 * (uintptr_t)v->dtype) &&
                  aligned(d_bmax, 4 * (uintptr_t)v->dtype);
     return from_hip(pdm::launch_plain_cached_x(a, bits, stream));
@@ -636,7 +660,10 @@ pdm_status pdm_plain_exact_distance_x(const pdm_volume* v, const void* d_volume,
                                       const float* h_alpha, uint8_t* d_dist, hipStream_t stream) {
     pdm::PlainArgs a;
     AlphaBits bits;
-    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits);
+    // the EXACT test looks every voxel up in the bitmap: at most
+    // PDM_MAX_EXACT_LEVELS (= PDM_MAX_PLAIN_BITMAP_LEVELS) levels, no runs
+    static_assert(PDM_MAX_EXACT_LEVELS == PDM_MAX_PLAIN_BITMAP_LEVELS, "EXACT plain bitmap");
+    const pdm_status st = plain_args(v, d_volume, h_alpha, d_dist, &a, &bits, false);
     if (st != PDM_OK) return st;
     return from_hip(pdm::launch_plain_exact_x(a, bits, stream));
 }

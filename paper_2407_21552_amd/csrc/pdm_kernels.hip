@@ -676,7 +676,35 @@ __device__ __forceinline__ bool any_bit(const uint32_t* __restrict__ words,
     return pre[wh] != pre[wl + 1];
 }
 
-template <typename T>
+// Whether [lo, hi] meets one of the nruns maximal runs of non-zero levels,
+// runs[j] = first | last << 16 in increasing order: the first run whose last
+// level is >= lo decides (binary search).
+__device__ __forceinline__ bool any_run(const uint32_t* __restrict__ runs, int nruns, uint32_t lo,
+                                        uint32_t hi) {
+    int l = 0, h = nruns;
+    while (l < h) {
+        const int mid = (l + h) >> 1;
+        if ((runs[mid] >> 16) < lo)
+            l = mid + 1;
+        else
+            h = mid;
+    }
+    return l < nruns && (runs[l] & 0xFFFFu) <= hi;
+}
+
+// The plain method's occupancy test of one brick [lo, hi]: the bitmap, or
+// with RUNS the run list (levels above the bitmap's 16384).
+template <bool RUNS>
+__device__ __forceinline__ bool any_alpha(const uint32_t* __restrict__ words,
+                                          const uint16_t* __restrict__ pre, int nwords, uint32_t lo,
+                                          uint32_t hi) {
+    if constexpr (RUNS)
+        return any_run(words, nwords, lo, hi);
+    else
+        return any_bit(words, pre, lo, hi);
+}
+
+template <typename T, bool RUNS>
 __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int nx, int ny, int nz,
                                                  int Bx, int By, int64_t rows, AlphaBits bits,
                                                  int nwords, int levels, uint8_t* __restrict__ dist,
@@ -709,7 +737,7 @@ __global__ void __launch_bounds__(256) k_plain_x(const T* __restrict__ vol, int 
             const QuadMinMax<T> r = s == 0 ? r0 : quad_minmax<T, false>(vol, nx, ny, nz, q, by, bz);
             const int nb = min(4, Bx - 4 * q);
             for (int k = 0; k < 4; ++k)
-                if (k < nb && any_bit(s_words, s_pre, umin(r.mn[k], top), umin(r.mx[k], top)))
+                if (k < nb && any_alpha<RUNS>(s_words, s_pre, nwords, umin(r.mn[k], top), umin(r.mx[k], top)))
                     o |= 1u << k;
         }
         s_nib[wv][s][lane] = (uint8_t)o;
@@ -767,7 +795,7 @@ __device__ __forceinline__ Quad<T> load_quad(const T* __restrict__ p, int64_t id
     return q;
 }
 
-template <typename T>
+template <typename T, bool RUNS>
 __global__ void __launch_bounds__(256) k_plain_cached_x(const T* __restrict__ bmin,
                                                         const T* __restrict__ bmax, int Bx,
                                                         int64_t rows, AlphaBits bits, int nwords,
@@ -784,7 +812,8 @@ __global__ void __launch_bounds__(256) k_plain_cached_x(const T* __restrict__ bm
         uint32_t o = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (k < nb && any_bit(s_words, s_pre, umin((uint32_t)a.v[k], top), umin((uint32_t)b.v[k], top)))
+            if (k < nb && any_alpha<RUNS>(s_words, s_pre, nwords, umin((uint32_t)a.v[k], top),
+                                          umin((uint32_t)b.v[k], top)))
                 o |= 1u << k;
         return o;
     };
@@ -2325,14 +2354,19 @@ hipError_t launch_pom_x(const PomArgs& a, const Bounds& b, hipStream_t s) {
 hipError_t launch_plain_x(const PlainArgs& a, const AlphaBits& bits, hipStream_t s) {
     const int64_t rows = (int64_t)a.By * a.Bz;
     const unsigned nb = blocks_for(rows, 4);
+    // run lists only above 16384 levels, so only for 16-bit volumes
     if (a.bytes == 1)
-        k_plain_x<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx, a.By,
-                                              rows, bits, a.nwords, a.levels, a.dist,
-                                              a.store_vec);
+        k_plain_x<uint8_t, false><<<nb, 256, 0, s>>>((const uint8_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                                     a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                                     a.store_vec);
+    else if (!a.runs)
+        k_plain_x<uint16_t, false><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                                      a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                                      a.store_vec);
     else
-        k_plain_x<uint16_t><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
-                                               a.By, rows, bits, a.nwords, a.levels, a.dist,
-                                               a.store_vec);
+        k_plain_x<uint16_t, true><<<nb, 256, 0, s>>>((const uint16_t*)a.vol, a.nx, a.ny, a.nz, a.Bx,
+                                                     a.By, rows, bits, a.nwords, a.levels, a.dist,
+                                                     a.store_vec);
     return hipGetLastError();
 }
 
@@ -2346,11 +2380,15 @@ hipError_t launch_plain_cached_x(const CachedArgs& a, const AlphaBits& bits, hip
     const int64_t blocks = (waves + 3) / 4;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     if (a.bytes == 1)
-        k_plain_cached_x<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(
+        k_plain_cached_x<uint8_t, false><<<(unsigned)blocks, 256, 0, s>>>(
             (const uint8_t*)a.bmin, (const uint8_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
             a.dist, a.store_vec, W, a.load_vec);
+    else if (!a.runs)
+        k_plain_cached_x<uint16_t, false><<<(unsigned)blocks, 256, 0, s>>>(
+            (const uint16_t*)a.bmin, (const uint16_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
+            a.dist, a.store_vec, W, a.load_vec);
     else
-        k_plain_cached_x<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(
+        k_plain_cached_x<uint16_t, true><<<(unsigned)blocks, 256, 0, s>>>(
             (const uint16_t*)a.bmin, (const uint16_t*)a.bmax, a.Bx, rows, bits, a.nwords, a.levels,
             a.dist, a.store_vec, W, a.load_vec);
     return hipGetLastError();

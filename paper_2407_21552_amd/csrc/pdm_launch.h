@@ -28,7 +28,9 @@ struct MapList {
     const uint8_t* src[256];
 };
 
-// Bit i set when alpha[i] != 0, passed by value.
+// The non-zero opacity levels, passed by value.  Up to 16384 levels: bit i
+// of w set when alpha[i] != 0, with per-word prefix counts.  Above that: the
+// maximal runs of non-zero levels, w[j] = first | last << 16, increasing.
 struct AlphaBits {
     uint32_t w[PDM_ALPHA_WORDS];
     uint16_t pre[PDM_ALPHA_WORDS + 2];  // pre[i] = set bits in w[0..i-1] (i <= nwords)
@@ -126,6 +128,7 @@ struct PlainArgs {
     uint8_t* dist;
     int nx, ny, nz, Bx, By, Bz, bytes, nwords, levels;
     int store_vec;
+    int runs;  // AlphaBits holds runs (nwords of them), not the bitmap
 };
 
 struct CachedArgs {
@@ -135,6 +138,7 @@ struct CachedArgs {
     int Bx, By, Bz, bytes, nwords, levels;
     int store_vec;  // packed stores of 4 distances allowed
     int load_vec;   // vector loads of 4 bricks' [min,max] allowed
+    int runs;       // AlphaBits holds runs (nwords of them), not the bitmap
 };
 
 struct PomExactArgs {

@@ -107,14 +107,31 @@ def test_bad_bounds_rejected_before_launch(lib, bounds, n):
     assert lib.pdm_active_set(pb, n, pa, 256, ctypes.c_void_p(m.ctypes.data)) == L.PDM_E_INVAL
 
 
-def test_plain_method_rejects_too_many_levels(lib):
-    d = desc(dtype=2, levels=16385)
-    alpha = np.ones(16385, np.float32)
+def test_plain_limits_match_the_header():
+    import re
+    text = open(L.HEADER).read()
+    defs = dict(re.findall(r"#define (PDM_\w+) (\d+)", text))
+    assert int(defs["PDM_MAX_PLAIN_RUNS"]) == L.MAX_PLAIN_RUNS
+    assert int(defs["PDM_MAX_PLAIN_BITMAP_LEVELS"]) == L.MAX_PLAIN_BITMAP_LEVELS
+
+
+def test_plain_method_rejects_too_many_runs(lib):
+    # above 16384 levels the non-zero opacity levels travel as runs: more
+    # than PDM_MAX_PLAIN_RUNS of them is refused before any device call
+    for levels in (16385, 65536):
+        d = desc(dtype=2, levels=levels)
+        alpha = np.zeros(levels, np.float32)
+        alpha[: 2 * (L.MAX_PLAIN_RUNS + 1) : 2] = 1.0   # one run more than accepted
+        assert lib.pdm_full_recompute(ctypes.byref(d), FAKE, ctypes.c_void_p(alpha.ctypes.data),
+                                      FAKE, NULL) == L.PDM_E_UNSUPPORTED
+        assert lib.pdm_full_recompute_cached(ctypes.byref(d), FAKE, FAKE,
+                                             ctypes.c_void_p(alpha.ctypes.data), FAKE,
+                                             NULL) == L.PDM_E_UNSUPPORTED
+    # 16-bit volumes of more than 65536 levels do not exist
+    d = desc(dtype=2, levels=65537)
+    alpha = np.ones(65537, np.float32)
     assert lib.pdm_full_recompute(ctypes.byref(d), FAKE, ctypes.c_void_p(alpha.ctypes.data),
-                                  FAKE, NULL) == L.PDM_E_UNSUPPORTED
-    assert lib.pdm_full_recompute_cached(ctypes.byref(d), FAKE, FAKE,
-                                         ctypes.c_void_p(alpha.ctypes.data), FAKE,
-                                         NULL) == L.PDM_E_UNSUPPORTED
+                                  FAKE, NULL) != L.PDM_OK
 
 
 def test_active_set_matches_oracle(orc):

@@ -53,20 +53,20 @@ def run_all(pdm, orc, vol, levels, bounds, alphas, label):
     dc = torch.empty_like(v.dist)
     for k, alpha in enumerate(alphas):
         mask = v.update_tf(alpha)
-        if levels <= 16384:
-            v.full_recompute(alpha, out=d)
-            v.full_recompute_cached(alpha, out=dc)
+        # above 16384 levels the plain method takes the TF's runs of non-zero
+        # opacity (a few for these TFs)
+        v.full_recompute(alpha, out=d)
+        v.full_recompute_cached(alpha, out=dc)
         torch.cuda.synchronize()
         dp, m = orc.tf_update(want, bounds, alpha, levels)
         np.testing.assert_array_equal(mask, m)
         np.testing.assert_array_equal(pdm.from_device(v.dist), dp, err_msg=f"D' tf {k}")
-        if levels <= 16384:
-            np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, levels),
-                                          err_msg=f"D tf {k}")
-            # plain method from the cached brick ranges: occupancy of the
-            # oracle's bricks under the TF, then its distance transform
-            want_c = orc.dt(orc.plain_occ_range(bmin, bmax, alpha, levels))
-            np.testing.assert_array_equal(pdm.from_device(dc), want_c, err_msg=f"D cached tf {k}")
+        np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, levels),
+                                      err_msg=f"D tf {k}")
+        # plain method from the cached brick ranges: occupancy of the
+        # oracle's bricks under the TF, then its distance transform
+        want_c = orc.dt(orc.plain_occ_range(bmin, bmax, alpha, levels))
+        np.testing.assert_array_equal(pdm.from_device(dc), want_c, err_msg=f"D cached tf {k}")
     return v
 
 
@@ -144,7 +144,7 @@ def random_case(seed):
 @pytest.mark.parametrize("seed", range(24))
 def test_random_cases(pdm, orc, seed):
     """Seeded random shapes (1 to 300 voxels per axis), intensity types and
-    level counts (u16 above 16384 levels: D' only), partitions at random
+    level counts (u16 up to 60000 levels), partitions at random
     borders (1 to 256 of them), volumes of random density and granularity:
     bricks, every PDM, and D', D and D from the cached ranges for three
     random TFs plus the empty, all-opaque and special-value TFs; the same in
@@ -196,6 +196,49 @@ def test_random_batches(pdm, orc, seed):
     for k, ((dp, m), it) in enumerate(zip(wants, upd)):
         np.testing.assert_array_equal(masks[k], m, err_msg=f"mask {k}")
         np.testing.assert_array_equal(pdm.from_device(it[4]).reshape(dp.shape), dp, err_msg=f"D' {k}")
+
+
+def test_plain_method_full_16bit_range(pdm, orc):
+    """16-bit volumes over all 65536 levels: the plain methods take the TF's
+    runs of non-zero opacity (up to 512 of them) instead of the bitmap.  D and
+    the cached D against the oracle for ramp TFs, a TF of exactly 512 runs
+    spread over the range and one run at each end; 513 runs are refused."""
+    import torch
+    rng = np.random.default_rng(65536)
+    L = 65536
+    shape = (37, 45, 70)
+    vol = blocky(shape, np.uint16, L, seed=65, keep=0.2, cell=2)
+    vol = np.where(rng.random(shape) < 0.01, rng.integers(0, L, size=shape), vol).astype(np.uint16)
+    bounds = W.uniform_bounds(L, 16)
+    v = pdm.Volume(pdm.to_device(vol), L, bounds, voxel_dtype=np.uint16)
+    v.build()
+    bmin, bmax = orc.bricks(vol)
+    alphas = tfs(L, 4, 66)
+    many = np.zeros(L, np.float32)
+    starts = np.sort(rng.choice(np.arange(0, L - 64, 64), size=pdm._lib.MAX_PLAIN_RUNS, replace=False))
+    for a in starts:
+        many[a:a + int(rng.integers(1, 40))] = 0.5      # runs separated by at least one zero level
+    ends = np.zeros(L, np.float32)
+    ends[:3] = 1.0
+    ends[-2:] = 1.0
+    alphas += [many, ends]
+    d = torch.empty_like(v.dist)
+    dc = torch.empty_like(v.dist)
+    say(f"[case] plain method over 65536 levels: shape={shape}, {len(alphas)} TFs")
+    for k, alpha in enumerate(alphas):
+        v.full_recompute(alpha, out=d)
+        v.full_recompute_cached(alpha, out=dc)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pdm.from_device(d), orc.full_recompute(vol, alpha, L),
+                                      err_msg=f"D tf {k}")
+        np.testing.assert_array_equal(pdm.from_device(dc),
+                                      orc.dt(orc.plain_occ_range(bmin, bmax, alpha, L)),
+                                      err_msg=f"D cached tf {k}")
+    too_many = many.copy()
+    too_many[L - 2] = 0.5    # one more run, apart from the others (they start below L - 64)
+    with pytest.raises(pdm.PdmError) as e:
+        v.full_recompute(too_many, out=d)
+    assert e.value.code == pdm._lib.PDM_E_UNSUPPORTED
 
 
 def test_capped_lines_closed_form(pdm, orc):
